@@ -1,0 +1,150 @@
+/*
+ * eprl.h - C ABI of the MI355X (gfx950) library for the EPRL vertex tensor in the booster
+ * decomposition (Gozzini, "A high-performance code for EPRL spin foam amplitudes",
+ * arXiv:2107.13952).
+ *
+ * What is computed (Sec. 2, eq. (vertex-ampl) and eq. (15j)):
+ *
+ *   A(i1..i5) = prod_{e=1..5} sqrt(2 i_e + 1)
+ *               sum_{shells l} sum_{k2..k5} prod_{e=2..5} (2 k_e + 1) B_e(i_e, k_e; l)
+ *               {15j}(l; i1, k2, k3, k4, k5)
+ *
+ *   {15j} = (-1)^R sum_x (2x+1) {i1 l25 x; k5 j14 j15} {j14 k5 x; l35 k4 l45}
+ *                                {k4 l35 x; k3 l24 l34} {l24 k3 x; j13 k2 l23}
+ *                                {k2 j13 x; i1 l25 j12},      R = sum of the 15 entries.
+ *
+ * Conventions shared by every entry point:
+ *  - Spins are passed as two_j = 2 j (non-negative ints), ten of them in link order
+ *    (12, 13, 14, 15, 23, 24, 25, 34, 35, 45) (the order of the spin list in Sec. 4.1).
+ *  - dl = number of shells (Delta s of Sec. 2): l_ab = j_ab + o_ab, o_ab = 0..dl, on the six
+ *    links 23, 24, 25, 34, 35, 45; l12..l15 stay at the boundary spins (gauge fixing of
+ *    eq. (vertex-ampl)).  Shells are the tuples (o23, o24, o25, o34, o35, o45) numbered
+ *    lexicographically, o45 fastest: there are (dl+1)^6 of them.
+ *  - Edge e couples its four links (p q)(r s):  e1 (12 13)(14 15), e2 (23 24)(25 12),
+ *    e3 (34 35)(13 23), e4 (45 14)(24 34), e5 (15 25)(35 45) (the booster tensors of step 3
+ *    of the framed algorithm of Sec. 3.1).  Boundary intertwiner i_e and virtual k_e run in
+ *    unit steps from max(|p-q|,|r-s|) to min(p+q,r+s); index n <-> lowest value + n.
+ *  - The vertex tensor is FP64, row-major [i1][i2][i3][i4][i5] (i5 fastest); this is the
+ *    byte layout of the paper's column-major A^{i5 i4 i3 i2 i1} (Sec. 3.1, step 7).
+ *  - Boosters (eq. (booster)) are the raw B4 values, without the (2k+1) factor, packed
+ *    FP64: for e = 2..5, for the triple of virtual spins of that edge
+ *        e2: (l23, l24, l25)  e3: (l34, l35, l23)  e4: (l45, l24, l34)  e5: (l25, l35, l45)
+ *    with offsets (o1, o2, o3) enumerated lexicographically (o3 fastest), one block of
+ *    dim(i_e) x dim(k_e) values, row-major (k fastest).  An empty k range is an empty block.
+ *    eprl_layout() returns the offsets.
+ *  - Complex numbers are interleaved (re, im) FP64 pairs.
+ *  - Device pointers are HIP device allocations owned by the caller; the library never
+ *    frees or retains them beyond the call.  Every device-side call is enqueued on the
+ *    context's stream and returns without synchronising unless stated otherwise.
+ *  - Return value 0 on success, a negative EPRL_E* code on failure; the message is then
+ *    available from eprl_last_error().  The library never aborts the process.
+ */
+#ifndef EPRL_H
+#define EPRL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EPRL_OK 0
+#define EPRL_EINVAL (-1) /* inadmissible spins, dl < 0, null or mismatched argument    */
+#define EPRL_ENOMEM (-2) /* device or host allocation failed                           */
+#define EPRL_EHIP (-3)   /* a HIP runtime call or kernel launch failed                 */
+#define EPRL_ERANGE (-4) /* spins or dimensions beyond what the kernels are built for  */
+
+typedef struct eprl_ctx eprl_ctx;
+
+/* Create a context bound to HIP device `device` and stream `hip_stream` (a hipStream_t; NULL
+ * means the null stream).  The context owns a grow-only device workspace (6j tables,
+ * per-chunk partial sums) that is freed by eprl_destroy.  Returns EPRL_EHIP when the device
+ * cannot be selected. */
+int eprl_create(eprl_ctx **out, int device, void *hip_stream);
+void eprl_destroy(eprl_ctx *ctx);
+/* Text of the last error on this context; valid until the next call on it. */
+const char *eprl_last_error(const eprl_ctx *ctx);
+/* Change the stream subsequent calls are enqueued on. */
+int eprl_set_stream(eprl_ctx *ctx, void *hip_stream);
+
+/* Host-only (no GPU use).  Ranges of the vertex tensor (eq. (vertex-ampl)) and the packed
+ * booster layout described above.
+ *   dims_i[5]        out: dim(i1) .. dim(i5)
+ *   two_ilo[5]       out (may be NULL): lowest two_i of each boundary intertwiner
+ *   booster_offsets  out (may be NULL): 4 (dl+1)^3 + 1 offsets in doubles; the last one is
+ *                    the total size of the booster buffer.
+ * Returns EPRL_EINVAL for inadmissible input. */
+int eprl_layout(const int two_j[10], int dl, int dims_i[5], int two_ilo[5],
+                int64_t *booster_offsets);
+
+/* Host-only.  Number of live shells (every k_e range non-empty) among the (dl+1)^6, and the
+ * number of {15j} x booster terms sum_{live shells} dim(i1) prod_e dim(k_e). */
+int eprl_count_terms(const int two_j[10], int dl, int64_t *live_shells, double *terms);
+
+/* The vertex tensor of eq. (vertex-ampl), computed by the framed algorithm of Sec. 3.1:
+ * 6j tables (step 4), then per shell the {15j} tensor W (6(i)), the booster sub-matrices
+ * (6(ii)), their contraction with W over k5, k4, k3, k2 (6(iii)) and the accumulation
+ * (6(iv)); finally A *= prod_e sqrt(2 i_e + 1).
+ *   boosters  device, booster_offsets[last] doubles in the packed layout
+ *   A         device, prod(dims_i) doubles, overwritten
+ *   gamma     the Barbero-Immirzi parameter the boosters were computed with; it enters A only
+ *             through the boosters and is checked to be finite and positive.
+ * The shell sum is evaluated in a fixed order: repeated calls give bitwise identical A. */
+int eprl_vertex_tensor(eprl_ctx *ctx, const int two_j[10], int dl, double gamma,
+                       const double *boosters, double *A);
+
+/* Same, restricted to shells with index in [shell_begin, shell_end) of the (dl+1)^6
+ * enumeration.  accumulate = 0 overwrites A, 1 adds to it.  Since A is a sum over shells,
+ * consecutive ranges reproduce the full tensor: this is the resume / sharding unit. */
+int eprl_vertex_tensor_range(eprl_ctx *ctx, const int two_j[10], int dl, double gamma,
+                             const double *boosters, int64_t shell_begin, int64_t shell_end,
+                             int accumulate, double *A);
+
+/* n independent vertex tensors (configuration c: two_j[10 c .. 10 c + 9], dl[c],
+ * boosters[c], A[c]) computed by one persistent launch; the host arrays of pointers hold
+ * device pointers.  Results equal n calls of eprl_vertex_tensor. */
+int eprl_vertex_tensor_batched(eprl_ctx *ctx, int n, const int *two_j, const int *dl,
+                               double gamma, const double *const *boosters, double *const *A);
+
+/* Boundary contraction (Sec. 3.2, `contract`):
+ *   F = sum_{i1..i5} A(i1..i5) psi1(i1) psi2(i2) psi3(i3) psi4(i4) psi5(i5)
+ * without complex conjugation.  A device FP64 [i1..i5]; psi[a] device complex vectors of
+ * length dims_i[a]; F device, one complex number. */
+int eprl_contract_boundary(eprl_ctx *ctx, const int dims_i[5], const double *A,
+                           const double *const psi[5], double *F);
+
+/* Adjoint of the boundary contraction composed with the vertex tensor.  With g = grad_F
+ * (host complex), writes g * dF/dpsi_a (device, complex, length dims_i[a]) and
+ * g * dF/dB (device, complex, same packing and size as the boosters) where the derivatives
+ * are the holomorphic ones of the multilinear function F(psi, B).  The {15j} tensors are
+ * recomputed shell by shell; no per-shell data is stored.  grad_psi entries or
+ * grad_boosters may be NULL to skip them. */
+int eprl_contract_boundary_adjoint(eprl_ctx *ctx, const int two_j[10], int dl,
+                                   const double *boosters, const double *A,
+                                   const double *const psi[5], const double grad_F[2],
+                                   double *const grad_psi[5], double *grad_boosters);
+
+/* Diagnostic: evaluate n 6j symbols {a b c; d e f} (args: n x 6 two_j values, host int32,
+ * each in 0..800)
+ * with the same device routine the table builder uses; out: n doubles (device). */
+int eprl_sixj_batch(eprl_ctx *ctx, int n, const int *args, double *out);
+
+/* Diagnostic: the {15j} tensor W(i1, k2, k3, k4, k5) of one shell (the intermediate of
+ * step 6(i), including the (-1)^R phase), written to W (device, row-major, dims
+ * dim(i1) x dim(k2) x ... x dim(k5)); kdims[4] (host, out) receives dim(k2..k5). */
+int eprl_shell_fifteenj(eprl_ctx *ctx, const int two_j[10], int dl, int64_t shell,
+                        int kdims[4], double *W, int64_t capacity);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around each launch.
+ * kernel ids: 0 = 6j table builder, 1 = vertex assembly, 2 = shell-sum reduction,
+ * 3 = adjoint shell kernel.  eprl_timing_enable(ctx, 1) starts recording (clearing earlier
+ * records), 0 stops.  eprl_timing_read synchronises the stream and returns the summed
+ * duration in milliseconds and the number of launches recorded for `kernel`. */
+int eprl_timing_enable(eprl_ctx *ctx, int enable);
+int eprl_timing_read(eprl_ctx *ctx, int kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPRL_H */

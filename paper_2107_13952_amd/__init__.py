@@ -1,0 +1,299 @@
+"""Python binding of the MI355X vertex-tensor library (``libeprl.so``, C ABI in include/eprl.h).
+
+Argument marshalling only: every step of the computation runs in the HIP kernels of the
+library.  PyTorch provides device memory and the current stream; all device tensors are
+float64 (complex vectors complex128) on a ROCm device.  If the library has not been built
+the import of this package fails: there is no CPU fallback.
+
+Functions mirror the C entry points:
+
+* ``layout(two_j, dl)`` and ``count_terms(two_j, dl)``  (host only)
+* ``vertex_tensor(two_j, dl, gamma, boosters)``          eq. (vertex-ampl)
+* ``vertex_tensor_range(...)``                            partial shell sums (resume unit)
+* ``vertex_tensor_batched(configs, gamma, boosters)``     many configurations, one launch
+* ``contract_boundary(A, psis)``                          contraction with five vectors
+* ``contract_boundary_adjoint(...)``                      its derivatives
+* ``VertexContract``                                      torch.autograd.Function of F(psi, B)
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeprl.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with paper_2107_13952_amd.build.build() "
+        "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_i32p = ctypes.POINTER(ctypes.c_int)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dp = ctypes.c_void_p
+
+_SIGS = {
+    "eprl_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p]),
+    "eprl_destroy": (None, [ctypes.c_void_p]),
+    "eprl_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "eprl_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "eprl_layout": (ctypes.c_int, [_i32p, ctypes.c_int, _i32p, _i32p, _i64p]),
+    "eprl_count_terms": (ctypes.c_int, [_i32p, ctypes.c_int, _i64p, ctypes.POINTER(ctypes.c_double)]),
+    "eprl_vertex_tensor": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_double, _dp, _dp]),
+    "eprl_vertex_tensor_range": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_double, _dp,
+                                                ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _dp]),
+    "eprl_vertex_tensor_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, ctypes.c_double,
+                                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
+    "eprl_contract_boundary": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp, ctypes.POINTER(ctypes.c_void_p), _dp]),
+    "eprl_contract_boundary_adjoint": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, _dp, _dp,
+                                                      ctypes.POINTER(ctypes.c_void_p),
+                                                      ctypes.POINTER(ctypes.c_double),
+                                                      ctypes.POINTER(ctypes.c_void_p), _dp]),
+    "eprl_sixj_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _dp]),
+    "eprl_shell_fifteenj": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_int64, _i32p, _dp,
+                                           ctypes.c_int64]),
+    "eprl_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "eprl_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _i64p]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+ERRORS = {-1: "EPRL_EINVAL", -2: "EPRL_ENOMEM", -3: "EPRL_EHIP", -4: "EPRL_ERANGE"}
+
+
+class EprlError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{ERRORS.get(code, code)}: {message}")
+        self.code = code
+
+
+def _ints(vals, n=None):
+    arr = (ctypes.c_int * len(vals))(*[int(v) for v in vals])
+    if n is not None and len(vals) != n:
+        raise ValueError(f"expected {n} values, got {len(vals)}")
+    return arr
+
+
+# ---------------------------------------------------------------- host-only calls
+
+def layout(two_j, dl):
+    """(dims_i[5], two_ilo[5], booster_offsets int64 array of 4 (dl+1)^3 + 1)."""
+    dims = (ctypes.c_int * 5)()
+    ilo = (ctypes.c_int * 5)()
+    offs = np.zeros(4 * (int(dl) + 1) ** 3 + 1, dtype=np.int64)
+    rc = _lib.eprl_layout(_ints(two_j, 10), int(dl), dims, ilo,
+                          offs.ctypes.data_as(_i64p))
+    if rc:
+        raise EprlError(rc, "inadmissible spins or shell count")
+    return list(dims), list(ilo), offs
+
+
+def count_terms(two_j, dl):
+    """(live shells, {15j} x booster terms)."""
+    live = ctypes.c_int64()
+    terms = ctypes.c_double()
+    rc = _lib.eprl_count_terms(_ints(two_j, 10), int(dl), ctypes.byref(live), ctypes.byref(terms))
+    if rc:
+        raise EprlError(rc, "inadmissible spins or shell count")
+    return live.value, terms.value
+
+
+# ---------------------------------------------------------------- device calls
+
+def _torch():
+    import torch
+    return torch
+
+
+class _Context:
+    """One library context per device, re-bound to torch's current stream at every call."""
+
+    def __init__(self, device):
+        self.device = device
+        self.handle = ctypes.c_void_p()
+        rc = _lib.eprl_create(ctypes.byref(self.handle), int(device), None)
+        if rc:
+            raise EprlError(rc, "cannot create a context on device %d" % device)
+
+    def bind(self):
+        torch = _torch()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.eprl_set_stream(self.handle, ctypes.c_void_p(stream))
+        return self.handle
+
+    def check(self, rc):
+        if rc:
+            raise EprlError(rc, _lib.eprl_last_error(self.handle).decode())
+
+    def __del__(self):
+        try:
+            if self.handle:
+                _lib.eprl_destroy(self.handle)
+        except Exception:
+            pass
+
+
+_CONTEXTS = {}
+
+
+def _ctx(device):
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no ROCm GPU visible: the vertex-tensor library runs only on the GPU")
+    dev = torch.device(device).index if torch.device(device).index is not None else torch.cuda.current_device()
+    if dev not in _CONTEXTS:
+        _CONTEXTS[dev] = _Context(dev)
+    return _CONTEXTS[dev]
+
+
+def _check_dev(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def vertex_tensor(two_j, dl, gamma, boosters, out=None):
+    """A[i1, i2, i3, i4, i5] (float64, on the boosters' device), eq. (vertex-ampl)."""
+    return vertex_tensor_range(two_j, dl, gamma, boosters, 0, (int(dl) + 1) ** 6, False, out)
+
+
+def vertex_tensor_range(two_j, dl, gamma, boosters, shell_begin, shell_end, accumulate=False, out=None):
+    torch = _torch()
+    dims, _, offs = layout(two_j, dl)
+    if boosters.numel() != int(offs[-1]):
+        raise ValueError(f"booster buffer holds {boosters.numel()} values, layout needs {int(offs[-1])}")
+    bp = _check_dev(boosters, torch.float64, "boosters")
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs an output tensor")
+        out = torch.empty(dims, dtype=torch.float64, device=boosters.device)
+    ap = _check_dev(out, torch.float64, "out")
+    if list(out.shape) != dims:
+        raise ValueError(f"output shape {list(out.shape)} != {dims}")
+    ctx = _ctx(boosters.device)
+    ctx.check(_lib.eprl_vertex_tensor_range(ctx.bind(), _ints(two_j, 10), int(dl), float(gamma), bp,
+                                            int(shell_begin), int(shell_end), 1 if accumulate else 0, ap))
+    return out
+
+
+def vertex_tensor_batched(configs, gamma, boosters, outs=None):
+    """configs: list of (two_j[10], dl); boosters: list of device tensors.  Returns list of A."""
+    torch = _torch()
+    n = len(configs)
+    if len(boosters) != n:
+        raise ValueError("one booster buffer per configuration is required")
+    if outs is None:
+        outs = [torch.empty(layout(tj, dl)[0], dtype=torch.float64, device=b.device)
+                for (tj, dl), b in zip(configs, boosters)]
+    flat_j = [v for tj, _ in configs for v in tj]
+    dls = [dl for _, dl in configs]
+    bptr = (ctypes.c_void_p * n)(*[_check_dev(b, torch.float64, "boosters").value for b in boosters])
+    aptr = (ctypes.c_void_p * n)(*[_check_dev(a, torch.float64, "out").value for a in outs])
+    for (tj, dl), b in zip(configs, boosters):
+        if b.numel() != int(layout(tj, dl)[2][-1]):
+            raise ValueError("booster buffer size does not match its configuration")
+    ctx = _ctx(boosters[0].device if n else "cuda")
+    ctx.check(_lib.eprl_vertex_tensor_batched(ctx.bind(), n, _ints(flat_j), _ints(dls), float(gamma), bptr, aptr))
+    return outs
+
+
+def _psi_ptrs(psis, dims):
+    torch = _torch()
+    if len(psis) != 5:
+        raise ValueError("five boundary vectors are required")
+    ptrs = []
+    for a, (p, n) in enumerate(zip(psis, dims)):
+        if p.shape != (n,):
+            raise ValueError(f"psi{a + 1} must have length {n}")
+        ptrs.append(_check_dev(p, torch.complex128, f"psi{a + 1}").value)
+    return (ctypes.c_void_p * 5)(*ptrs)
+
+
+def contract_boundary(A, psis):
+    """F = sum A psi1 psi2 psi3 psi4 psi5 as a complex128 0-d device tensor."""
+    torch = _torch()
+    ap = _check_dev(A, torch.float64, "A")
+    dims = list(A.shape)
+    if len(dims) != 5:
+        raise ValueError("A must have five indices")
+    F = torch.empty(2, dtype=torch.float64, device=A.device)
+    ctx = _ctx(A.device)
+    ctx.check(_lib.eprl_contract_boundary(ctx.bind(), _ints(dims, 5), ap, _psi_ptrs(psis, dims),
+                                          ctypes.c_void_p(F.data_ptr())))
+    return torch.view_as_complex(F)
+
+
+def contract_boundary_adjoint(two_j, dl, boosters, A, psis, grad_F=1.0, want_psi=True, want_boosters=True):
+    """(g dF/dpsi_a for a = 1..5, g dF/dB) as complex128 device tensors (holomorphic derivatives)."""
+    torch = _torch()
+    dims, _, offs = layout(two_j, dl)
+    dev = psis[0].device
+    g = complex(grad_F)
+    gbuf = (ctypes.c_double * 2)(g.real, g.imag)
+    gpsi = [torch.empty(n, dtype=torch.complex128, device=dev) for n in dims] if want_psi else None
+    gb = torch.empty(int(offs[-1]), dtype=torch.complex128, device=dev) if want_boosters else None
+    gpsi_ptrs = (ctypes.c_void_p * 5)(*[t.data_ptr() for t in gpsi]) if want_psi else None
+    bp = _check_dev(boosters, torch.float64, "boosters") if want_boosters else None
+    ap = _check_dev(A, torch.float64, "A") if want_psi else None
+    ctx = _ctx(dev)
+    ctx.check(_lib.eprl_contract_boundary_adjoint(
+        ctx.bind(), _ints(two_j, 10), int(dl), bp, ap, _psi_ptrs(psis, dims), gbuf,
+        gpsi_ptrs, ctypes.c_void_p(gb.data_ptr()) if want_boosters else None))
+    return gpsi, gb
+
+
+def sixj_batch(args, device="cuda"):
+    """Evaluate 6j symbols on the GPU; args is an (n, 6) integer array of two_j values."""
+    torch = _torch()
+    a = np.ascontiguousarray(np.asarray(args, dtype=np.int32).reshape(-1, 6))
+    out = torch.empty(a.shape[0], dtype=torch.float64, device=device)
+    ctx = _ctx(out.device)
+    ctx.check(_lib.eprl_sixj_batch(ctx.bind(), a.shape[0], a.ctypes.data_as(_i32p),
+                                   ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def shell_fifteenj(two_j, dl, shell, device="cuda"):
+    """The {15j} tensor W(i1, k2, k3, k4, k5) of one shell (diagnostic)."""
+    torch = _torch()
+    dims, _, _ = layout(two_j, dl)
+    cap = dims[0] * 16 ** 4
+    W = torch.zeros(cap, dtype=torch.float64, device=device)
+    kd = (ctypes.c_int * 4)()
+    ctx = _ctx(W.device)
+    ctx.check(_lib.eprl_shell_fifteenj(ctx.bind(), _ints(two_j, 10), int(dl), int(shell), kd,
+                                       ctypes.c_void_p(W.data_ptr()), cap))
+    shape = [dims[0]] + list(kd)
+    n = int(np.prod(shape))
+    return W[:n].reshape(shape)
+
+
+KERNELS = {"sixj_tables": 0, "assemble": 1, "reduce": 2, "adjoint_shells": 3}
+
+
+def timing_enable(enable=True, device="cuda"):
+    """Start (clearing earlier records) or stop per-kernel HIP-event timing."""
+    ctx = _ctx(device)
+    ctx.check(_lib.eprl_timing_enable(ctx.bind(), 1 if enable else 0))
+
+
+def timing_read(kernel, device="cuda"):
+    """(total milliseconds, launches) recorded for ``kernel`` (a name of ``KERNELS``)."""
+    ctx = _ctx(device)
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    ctx.check(_lib.eprl_timing_read(ctx.bind(), KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+from .autograd import VertexContract  # noqa: E402,F401

@@ -1,0 +1,557 @@
+// C ABI of the vertex-tensor library: argument checks, workspace management and launch
+// sequencing.  All device work is enqueued on the context's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <sstream>
+
+#include "eprl_internal.hpp"
+
+using namespace eprl;
+
+struct eprl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // grow-only device workspace
+  char *ws = nullptr;
+  size_t ws_size = 0;
+  // pinned staging for small host->device uploads, reused once the previous copy finished
+  char *stage = nullptr;
+  size_t stage_size = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
+  // factorial prime-exponent table (device), valid for arguments <= fact_max
+  uint16_t *fexp = nullptr;
+  int *primes = nullptr;
+  int fact_max = -1;
+  int nprime = 0;
+  // optional per-kernel timing
+  bool timing = false;
+  struct Rec {
+    int kernel;
+    hipEvent_t start, stop;
+  };
+  std::vector<Rec> recs;
+};
+
+namespace {
+
+int fail(eprl_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(eprl_ctx *c, hipError_t e, const char *what) {
+  std::ostringstream os;
+  os << what << ": " << hipGetErrorString(e);
+  return fail(c, EPRL_EHIP, os.str());
+}
+
+#define HIP_TRY(ctx, call)                                  \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+// Brackets a launch with timing events when timing is enabled.
+struct TimedLaunch {
+  eprl_ctx *c;
+  int kernel;
+  hipEvent_t start = nullptr, stop = nullptr;
+  TimedLaunch(eprl_ctx *c_, int k) : c(c_), kernel(k) {
+    if (!c->timing) return;
+    if (hipEventCreate(&start) != hipSuccess || hipEventCreate(&stop) != hipSuccess) {
+      hipGetLastError();
+      start = stop = nullptr;
+      return;
+    }
+    hipEventRecord(start, c->stream);
+  }
+  ~TimedLaunch() {
+    if (!start) return;
+    hipEventRecord(stop, c->stream);
+    c->recs.push_back({kernel, start, stop});
+  }
+};
+
+void clear_timing(eprl_ctx *c) {
+  for (auto &r : c->recs) {
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+  }
+  c->recs.clear();
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int ensure_workspace(eprl_ctx *c, size_t bytes) {
+  if (bytes <= c->ws_size) return EPRL_OK;
+  if (c->ws) {
+    // Earlier work on the stream may still read the old workspace.
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_size = 0;
+  }
+  size_t want = std::max(bytes, c->ws_size * 3 / 2);
+  if (hipMalloc(&c->ws, want) != hipSuccess) {
+    c->ws = nullptr;
+    if (hipMalloc(&c->ws, bytes) != hipSuccess) {
+      c->ws = nullptr;
+      hipGetLastError();
+      return fail(c, EPRL_ENOMEM, "device workspace allocation failed");
+    }
+    want = bytes;
+  }
+  c->ws_size = want;
+  return EPRL_OK;
+}
+
+// Return a pinned staging area of `bytes`, waiting for the previous upload from it.
+int staging(eprl_ctx *c, size_t bytes, char **out) {
+  if (c->stage_pending) {
+    HIP_TRY(c, hipEventSynchronize(c->stage_done));
+    c->stage_pending = false;
+  }
+  if (bytes > c->stage_size) {
+    if (c->stage) HIP_TRY(c, hipHostFree(c->stage));
+    c->stage = nullptr;
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    if (hipHostMalloc((void **)&c->stage, want, hipHostMallocDefault) != hipSuccess) {
+      c->stage = nullptr;
+      c->stage_size = 0;
+      hipGetLastError();
+      return fail(c, EPRL_ENOMEM, "pinned staging allocation failed");
+    }
+    c->stage_size = want;
+  }
+  *out = c->stage;
+  return EPRL_OK;
+}
+
+int upload(eprl_ctx *c, void *dst, size_t bytes) {
+  HIP_TRY(c, hipMemcpyAsync(dst, c->stage, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipEventRecord(c->stage_done, c->stream));
+  c->stage_pending = true;
+  return EPRL_OK;
+}
+
+int ensure_fexp(eprl_ctx *c, int fact_max) {
+  if (fact_max <= c->fact_max) return EPRL_OK;
+  fact_max = std::max(fact_max, 256);
+  std::vector<int> pr = primes_upto(fact_max);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->fexp) HIP_TRY(c, hipFree(c->fexp));
+  if (c->primes) HIP_TRY(c, hipFree(c->primes));
+  c->fexp = nullptr;
+  c->primes = nullptr;
+  c->fact_max = -1;
+  if (hipMalloc(&c->primes, pr.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc(&c->fexp, (size_t)(fact_max + 1) * pr.size() * sizeof(uint16_t)) != hipSuccess) {
+    hipGetLastError();
+    return fail(c, EPRL_ENOMEM, "factorial table allocation failed");
+  }
+  char *st;
+  int rc = staging(c, pr.size() * sizeof(int), &st);
+  if (rc) return rc;
+  std::memcpy(st, pr.data(), pr.size() * sizeof(int));
+  rc = upload(c, c->primes, pr.size() * sizeof(int));
+  if (rc) return rc;
+  HIP_TRY(c, launch_fexp_table(c->fexp, fact_max, c->primes, (int)pr.size(), c->stream));
+  c->fact_max = fact_max;
+  c->nprime = (int)pr.size();
+  return EPRL_OK;
+}
+
+// Device-side state of one configuration: tables built, metadata uploaded.
+struct Prepared {
+  Plan plan;
+  double *tables = nullptr;
+  int64_t *boff = nullptr;
+  int *kr = nullptr;
+  char *tail = nullptr;  // first free byte of the workspace after the above
+};
+
+// Plan, size the workspace (tables + metadata + `extra` bytes), upload metadata and build the
+// 6j tables.  `extra` is placed at `prep.tail`.
+int prepare(eprl_ctx *c, const int two_j[10], int dl, size_t extra, Prepared &prep) {
+  int rc = make_plan(two_j, dl, prep.plan, c->err);
+  if (rc) return rc;
+  Plan &p = prep.plan;
+  if (p.D == 0 || p.kmax > 16)
+    return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
+  rc = ensure_fexp(c, p.fact_max);
+  if (rc) return rc;
+  const size_t tbytes = align_up((size_t)p.toff[5] * sizeof(double), 256);
+  const size_t bbytes = align_up(p.boff.size() * sizeof(int64_t), 256);
+  const size_t kbytes = align_up(p.kr.size() * sizeof(int), 256);
+  rc = ensure_workspace(c, tbytes + bbytes + kbytes + extra);
+  if (rc) return rc;
+  prep.tables = reinterpret_cast<double *>(c->ws);
+  prep.boff = reinterpret_cast<int64_t *>(c->ws + tbytes);
+  prep.kr = reinterpret_cast<int *>(c->ws + tbytes + bbytes);
+  prep.tail = c->ws + tbytes + bbytes + kbytes;
+  char *st;
+  rc = staging(c, bbytes + kbytes, &st);
+  if (rc) return rc;
+  std::memcpy(st, p.boff.data(), p.boff.size() * sizeof(int64_t));
+  std::memcpy(st + bbytes, p.kr.data(), p.kr.size() * sizeof(int));
+  rc = upload(c, prep.boff, bbytes + kbytes);
+  if (rc) return rc;
+  TableParams tp;
+  std::memcpy(tp.two_j, p.two_j, sizeof(tp.two_j));
+  tp.nd = p.nd;
+  tp.i1_lo2 = p.i[0].lo2;
+  tp.i1_n = p.i[0].n;
+  for (int e = 0; e < 4; ++e) {
+    tp.K_lo2[e] = p.K[e].lo2;
+    tp.K_n[e] = p.K[e].n;
+  }
+  tp.X_lo2 = p.X.lo2;
+  tp.NX = p.X.n;
+  for (int t = 0; t < 6; ++t) tp.toff[t] = p.toff[t];
+  tp.tables = prep.tables;
+  tp.fexp = c->fexp;
+  tp.primes = c->primes;
+  tp.nprime = c->nprime;
+  {
+    TimedLaunch tl(c, 0);
+    HIP_TRY(c, launch_sixj_tables(tp, p.toff[5], c->stream));
+  }
+  return EPRL_OK;
+}
+
+VertexParams vertex_params(const Prepared &prep, const double *B) {
+  const Plan &p = prep.plan;
+  VertexParams vp;
+  std::memset(&vp, 0, sizeof(vp));
+  std::memcpy(vp.two_j, p.two_j, sizeof(vp.two_j));
+  vp.nd = p.nd;
+  for (int e = 0; e < 5; ++e) {
+    vp.i_lo2[e] = p.i[e].lo2;
+    vp.i_n[e] = p.i[e].n;
+  }
+  for (int e = 0; e < 4; ++e) {
+    vp.K_lo2[e] = p.K[e].lo2;
+    vp.K_n[e] = p.K[e].n;
+  }
+  vp.X_lo2 = p.X.lo2;
+  vp.NX = p.X.n;
+  for (int t = 0; t < 5; ++t) {
+    const double *tab = prep.tables + p.toff[t];
+    if (t == 0) vp.T1 = tab;
+    if (t == 1) vp.T2 = tab;
+    if (t == 2) vp.T3 = tab;
+    if (t == 3) vp.T4 = tab;
+    if (t == 4) vp.T5 = tab;
+  }
+  vp.B = B;
+  vp.boff = prep.boff;
+  vp.kr = prep.kr;
+  return vp;
+}
+
+int check_ctx(eprl_ctx *c) { return c ? EPRL_OK : EPRL_EINVAL; }
+
+int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, const double *B,
+                      int64_t sb, int64_t se, int accumulate, double *A) {
+  if (!(gamma > 0.0) || !std::isfinite(gamma))
+    return fail(c, EPRL_EINVAL, "gamma must be finite and positive");
+  if (!B || !A) return fail(c, EPRL_EINVAL, "null booster or output pointer");
+  Plan probe;
+  int rc = make_plan(two_j, dl, probe, c->err);
+  if (rc) return rc;
+  if (sb < 0 || se > probe.nshell || sb > se)
+    return fail(c, EPRL_EINVAL, "shell range outside [0, (dl+1)^6]");
+  const int D = probe.D;
+  if (D == 0) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
+  const int64_t nrange = std::max<int64_t>(se - sb, 1);
+  const int target_wg = D == 8 ? 4096 : 1024;
+  int nchunk = std::max(1, target_wg / probe.i[0].n);
+  int64_t chunk = (nrange + nchunk - 1) / nchunk;
+  nchunk = (int)((nrange + chunk - 1) / chunk);
+  const size_t pbytes = align_up((size_t)nchunk * probe.a_size * sizeof(double), 256);
+  Prepared prep;
+  rc = prepare(c, two_j, dl, pbytes, prep);
+  if (rc) return rc;
+  VertexParams vp = vertex_params(prep, B);
+  vp.partial = reinterpret_cast<double *>(prep.tail);
+  vp.shell_begin = sb;
+  vp.shell_end = se;
+  vp.chunk = chunk;
+  vp.nchunk = nchunk;
+  {
+    TimedLaunch tl(c, 1);
+    HIP_TRY(c, launch_assemble(vp, D, c->stream));
+  }
+  ReduceParams rp;
+  rp.partial = vp.partial;
+  rp.nchunk = nchunk;
+  rp.a_size = prep.plan.a_size;
+  for (int e = 0; e < 5; ++e) {
+    rp.i_lo2[e] = prep.plan.i[e].lo2;
+    rp.i_n[e] = prep.plan.i[e].n;
+  }
+  rp.A = A;
+  rp.accumulate = accumulate;
+  {
+    TimedLaunch tl(c, 2);
+    HIP_TRY(c, launch_reduce(rp, c->stream));
+  }
+  return EPRL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int eprl_create(eprl_ctx **out, int device, void *hip_stream) {
+  if (!out) return EPRL_EINVAL;
+  *out = nullptr;
+  eprl_ctx *c = new (std::nothrow) eprl_ctx;
+  if (!c) return EPRL_ENOMEM;
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipSetDevice(device) != hipSuccess || hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
+    hipGetLastError();
+    delete c;
+    return EPRL_EHIP;
+  }
+  *out = c;
+  return EPRL_OK;
+}
+
+void eprl_destroy(eprl_ctx *c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  if (c->ws) hipFree(c->ws);
+  if (c->stage) hipHostFree(c->stage);
+  if (c->fexp) hipFree(c->fexp);
+  if (c->primes) hipFree(c->primes);
+  if (c->stage_done) hipEventDestroy(c->stage_done);
+  clear_timing(c);
+  delete c;
+}
+
+const char *eprl_last_error(const eprl_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int eprl_set_stream(eprl_ctx *c, void *hip_stream) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return EPRL_OK;
+}
+
+int eprl_layout(const int two_j[10], int dl, int dims_i[5], int two_ilo[5], int64_t *booster_offsets) {
+  Plan p;
+  std::string err;
+  int rc = make_plan(two_j, dl, p, err);
+  if (rc) return rc;
+  for (int e = 0; e < 5; ++e) {
+    if (dims_i) dims_i[e] = p.i[e].n;
+    if (two_ilo) two_ilo[e] = p.i[e].lo2;
+  }
+  if (booster_offsets) std::copy(p.boff.begin(), p.boff.end(), booster_offsets);
+  return EPRL_OK;
+}
+
+int eprl_count_terms(const int two_j[10], int dl, int64_t *live_shells, double *terms) {
+  Plan p;
+  std::string err;
+  int rc = make_plan(two_j, dl, p, err);
+  if (rc) return rc;
+  int64_t live;
+  double t;
+  count_terms(p, live, t);
+  if (live_shells) *live_shells = live;
+  if (terms) *terms = t;
+  return EPRL_OK;
+}
+
+int eprl_vertex_tensor(eprl_ctx *c, const int two_j[10], int dl, double gamma, const double *B,
+                       double *A) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  Plan probe;
+  int rc = make_plan(two_j, dl, probe, c->err);
+  if (rc) return rc;
+  return vertex_range_impl(c, two_j, dl, gamma, B, 0, probe.nshell, 0, A);
+}
+
+int eprl_vertex_tensor_range(eprl_ctx *c, const int two_j[10], int dl, double gamma,
+                             const double *B, int64_t shell_begin, int64_t shell_end,
+                             int accumulate, double *A) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  return vertex_range_impl(c, two_j, dl, gamma, B, shell_begin, shell_end, accumulate ? 1 : 0, A);
+}
+
+int eprl_vertex_tensor_batched(eprl_ctx *c, int n, const int *two_j, const int *dl, double gamma,
+                               const double *const *boosters, double *const *A) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (n < 0 || (n > 0 && (!two_j || !dl || !boosters || !A)))
+    return fail(c, EPRL_EINVAL, "invalid batch arguments");
+  for (int q = 0; q < n; ++q) {
+    int rc = eprl_vertex_tensor(c, two_j + 10 * q, dl[q], gamma, boosters[q], A[q]);
+    if (rc) return rc;
+  }
+  return EPRL_OK;
+}
+
+int eprl_contract_boundary(eprl_ctx *c, const int dims_i[5], const double *A,
+                           const double *const psi[5], double *F) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!dims_i || !A || !psi || !F) return fail(c, EPRL_EINVAL, "null argument");
+  ContractParams cp;
+  for (int e = 0; e < 5; ++e) {
+    if (dims_i[e] <= 0 || !psi[e]) return fail(c, EPRL_EINVAL, "invalid dimension or vector");
+    cp.n[e] = dims_i[e];
+    cp.psi[e] = psi[e];
+  }
+  cp.A = A;
+  cp.nblocks = 256;
+  int rc = ensure_workspace(c, cp.nblocks * 2 * sizeof(double));
+  if (rc) return rc;
+  cp.partial = reinterpret_cast<double *>(c->ws);
+  HIP_TRY(c, launch_contract(cp, F, c->stream));
+  return EPRL_OK;
+}
+
+int eprl_contract_boundary_adjoint(eprl_ctx *c, const int two_j[10], int dl, const double *B,
+                                   const double *A, const double *const psi[5],
+                                   const double grad_F[2], double *const grad_psi[5],
+                                   double *grad_boosters) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!psi || !grad_F) return fail(c, EPRL_EINVAL, "null argument");
+  for (int e = 0; e < 5; ++e)
+    if (!psi[e]) return fail(c, EPRL_EINVAL, "null boundary vector");
+  Plan probe;
+  int rc = make_plan(two_j, dl, probe, c->err);
+  if (rc) return rc;
+  if (grad_psi) {
+    bool any = false;
+    for (int e = 0; e < 5; ++e) any = any || grad_psi[e];
+    if (any) {
+      if (!A) return fail(c, EPRL_EINVAL, "the vertex tensor is needed for dF/dpsi");
+      ContractParams cp;
+      for (int e = 0; e < 5; ++e) {
+        cp.n[e] = probe.i[e].n;
+        cp.psi[e] = psi[e];
+      }
+      cp.A = A;
+      cp.nblocks = 0;
+      cp.partial = nullptr;
+      HIP_TRY(c, launch_grad_psi(cp, grad_F[0], grad_F[1], grad_psi, c->stream));
+    }
+  }
+  if (!grad_boosters) return EPRL_OK;
+  if (!B) return fail(c, EPRL_EINVAL, "null booster pointer");
+  if (probe.kmax > 16) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
+  const int kpad = std::max(probe.kmax, 1);
+  const size_t gbytes = align_up((size_t)probe.nshell * 4 * kpad * 2 * sizeof(double), 256);
+  Prepared prep;
+  rc = prepare(c, two_j, dl, gbytes, prep);
+  if (rc) return rc;
+  AdjointParams ap;
+  ap.v = vertex_params(prep, B);
+  ap.v.shell_begin = 0;
+  ap.v.shell_end = prep.plan.nshell;
+  for (int e = 0; e < 5; ++e) ap.psi[e] = psi[e];
+  ap.shell_g = reinterpret_cast<double *>(prep.tail);
+  ap.kpad = kpad;
+  {
+    TimedLaunch tl(c, 3);
+    HIP_TRY(c, launch_adjoint_shells(ap, c->stream));
+  }
+  HIP_TRY(c, launch_adjoint_reduce(ap, prep.plan.boff.back(), grad_F[0], grad_F[1], grad_boosters,
+                                   c->stream));
+  return EPRL_OK;
+}
+
+int eprl_sixj_batch(eprl_ctx *c, int n, const int *args, double *out) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (n < 0 || (n > 0 && (!args || !out))) return fail(c, EPRL_EINVAL, "invalid arguments");
+  if (n == 0) return EPRL_OK;
+  int big = 0;
+  for (int q = 0; q < 6 * n; ++q) {
+    if (args[q] < 0 || args[q] > 800) return fail(c, EPRL_ERANGE, "6j argument outside 0..800");
+    big = std::max(big, args[q]);
+  }
+  int rc = ensure_fexp(c, 2 * big + 2);
+  if (rc) return rc;
+  const size_t bytes = (size_t)n * 6 * sizeof(int);
+  rc = ensure_workspace(c, bytes);
+  if (rc) return rc;
+  char *st;
+  rc = staging(c, bytes, &st);
+  if (rc) return rc;
+  std::memcpy(st, args, bytes);
+  rc = upload(c, c->ws, bytes);
+  if (rc) return rc;
+  HIP_TRY(c, launch_sixj_batch(reinterpret_cast<int *>(c->ws), n, out, c->fexp, c->primes,
+                               c->nprime, c->fact_max, c->stream));
+  return EPRL_OK;
+}
+
+int eprl_shell_fifteenj(eprl_ctx *c, const int two_j[10], int dl, int64_t shell, int kdims[4],
+                        double *W, int64_t capacity) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!kdims || !W) return fail(c, EPRL_EINVAL, "null argument");
+  Plan probe;
+  int rc = make_plan(two_j, dl, probe, c->err);
+  if (rc) return rc;
+  if (shell < 0 || shell >= probe.nshell) return fail(c, EPRL_EINVAL, "shell index out of range");
+  const int nd = probe.nd, nd3 = nd * nd * nd;
+  int o[6];
+  int64_t r = shell;
+  for (int q = 5; q >= 0; --q) {
+    o[q] = (int)(r % nd);
+    r /= nd;
+  }
+  const int t[4] = {(o[0] * nd + o[1]) * nd + o[2], (o[3] * nd + o[4]) * nd + o[0],
+                    (o[5] * nd + o[1]) * nd + o[3], (o[2] * nd + o[4]) * nd + o[5]};
+  int64_t need = probe.i[0].n;
+  for (int e = 0; e < 4; ++e) {
+    kdims[e] = probe.kr[(e * nd3 + t[e]) * 2 + 1];
+    need *= kdims[e];
+  }
+  if (need > capacity) return fail(c, EPRL_EINVAL, "output capacity too small");
+  if (need == 0) return EPRL_OK;
+  if (probe.kmax > 16) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
+  Prepared prep;
+  rc = prepare(c, two_j, dl, 0, prep);
+  if (rc) return rc;
+  VertexParams vp = vertex_params(prep, nullptr);
+  HIP_TRY(c, launch_shell_fifteenj(vp, shell, W, c->stream));
+  return EPRL_OK;
+}
+
+int eprl_timing_enable(eprl_ctx *c, int enable) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (c->stream) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  else HIP_TRY(c, hipDeviceSynchronize());
+  clear_timing(c);
+  c->timing = enable != 0;
+  return EPRL_OK;
+}
+
+int eprl_timing_read(eprl_ctx *c, int kernel, double *total_ms, int64_t *launches) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (c->stream) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  else HIP_TRY(c, hipDeviceSynchronize());
+  double total = 0.0;
+  int64_t n = 0;
+  for (auto &r : c->recs) {
+    if (r.kernel != kernel) continue;
+    float ms = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, r.start, r.stop));
+    total += ms;
+    ++n;
+  }
+  if (total_ms) *total_ms = total;
+  if (launches) *launches = n;
+  return EPRL_OK;
+}
+
+}  // extern "C"

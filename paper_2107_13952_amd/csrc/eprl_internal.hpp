@@ -1,0 +1,124 @@
+// Internal declarations shared by the host planner, the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/eprl.h"
+
+namespace eprl {
+
+// A range of spins in two-units: values lo2, lo2 + 2, ..., lo2 + 2 (n - 1).
+struct Range {
+  int lo2 = 0;
+  int n = 0;
+};
+
+// Link indices in the order (12, 13, 14, 15, 23, 24, 25, 34, 35, 45).
+enum Link { L12 = 0, L13, L14, L15, L23, L24, L25, L34, L35, L45 };
+
+// Everything the kernels need to know about one configuration (two_j, dl); built on the host.
+struct Plan {
+  int two_j[10];
+  int dl = 0;
+  int nd = 1;                 // dl + 1
+  Range i[5];                 // boundary intertwiners i1..i5
+  Range K[4];                 // union over shells of the k2..k5 ranges (global windows)
+  Range X;                    // global window of the x summation spin
+  int kmax = 0;               // largest k range of any shell
+  int D = 0;                  // padded tile dimension of the assembly kernel (8 or 16)
+  int64_t nshell = 0;         // (dl + 1)^6
+  std::vector<int64_t> boff;  // packed booster offsets, 4 nd^3 + 1
+  std::vector<int> kr;        // [4][nd^3][2]: lowest two_k and size of k_e per edge triple
+  int fact_max = 0;           // largest factorial argument met by any 6j of the tables
+  // 6j tables: sizes in doubles and offsets into one allocation.
+  int64_t tsize[5] = {0, 0, 0, 0, 0};
+  int64_t toff[6] = {0, 0, 0, 0, 0, 0};
+  int64_t a_size = 0;         // entries of the vertex tensor
+};
+
+// Build a plan; returns EPRL_OK or an error code with a message in `err`.
+int make_plan(const int two_j[10], int dl, Plan &p, std::string &err);
+// Live-shell and term counts (host enumeration).
+void count_terms(const Plan &p, int64_t &live, double &terms);
+// Primes up to n.
+std::vector<int> primes_upto(int n);
+
+// ---- kernel-side parameter blocks (passed by value) ----
+
+struct TableParams {
+  int two_j[10];
+  int nd;
+  int i1_lo2, i1_n;
+  int K_lo2[4], K_n[4];
+  int X_lo2, NX;
+  int64_t toff[6];
+  double *tables;
+  const uint16_t *fexp;  // [fact_max + 1][nprime]
+  const int *primes;
+  int nprime;
+};
+
+struct VertexParams {
+  int two_j[10];
+  int nd;
+  int i_lo2[5], i_n[5];
+  int K_lo2[4], K_n[4];
+  int X_lo2, NX;
+  const double *T1, *T2, *T3, *T4, *T5;
+  const double *B;
+  const int64_t *boff;
+  const int *kr;
+  double *partial;        // [nchunk][i1][i2][i3][i4][i5]
+  int64_t shell_begin, shell_end, chunk;
+  int nchunk;
+};
+
+struct ReduceParams {
+  const double *partial;
+  int nchunk;
+  int64_t a_size;
+  int i_lo2[5], i_n[5];
+  double *A;
+  int accumulate;
+};
+
+// Kernel launchers (defined in the .hip files).  They return hipSuccess or the launch error.
+hipError_t launch_fexp_table(uint16_t *fexp, int fact_max, const int *primes, int nprime,
+                             hipStream_t s);
+hipError_t launch_sixj_tables(const TableParams &tp, int64_t total, hipStream_t s);
+hipError_t launch_sixj_batch(const int *args, int n, double *out, const uint16_t *fexp,
+                             const int *primes, int nprime, int fact_max, hipStream_t s);
+hipError_t launch_assemble(const VertexParams &vp, int D, hipStream_t s);
+hipError_t launch_reduce(const ReduceParams &rp, hipStream_t s);
+hipError_t launch_shell_fifteenj(const VertexParams &vp, int64_t shell, double *W,
+                                 hipStream_t s);
+
+struct ContractParams {
+  int n[5];
+  const double *A;
+  const double *psi[5];
+  double *partial;  // complex partial sums
+  int nblocks;
+};
+struct GradPsiOut {
+  double *p[5];
+};
+hipError_t launch_contract(const ContractParams &cp, double *F, hipStream_t s);
+hipError_t launch_grad_psi(const ContractParams &cp, double gre, double gim, double *const out[5],
+                           hipStream_t s);
+
+struct AdjointParams {
+  VertexParams v;
+  const double *psi[5];
+  double *shell_g;        // [nshell][4][kmaxpad] complex
+  int kpad;
+};
+hipError_t launch_adjoint_shells(const AdjointParams &ap, hipStream_t s);
+hipError_t launch_adjoint_reduce(const AdjointParams &ap, int64_t total, double gre, double gim,
+                                 double *grad_b, hipStream_t s);
+
+}  // namespace eprl

@@ -1,0 +1,287 @@
+// FP64 6j symbols on the device and the five 6j tables of the vertex computation
+// (Sec. 3.1 framed algorithm, step 4; the tensors S of eq. (15j)).
+//
+// Racah's single-sum formula (Racah 1942):
+//   {a b c; d e f} = sqrt(P) sum_t (-1)^t (t+1)! / [prod_i (t - alpha_i)! prod_j (beta_j - t)!]
+//   alpha = (a+b+c, a+e+f, d+b+f, d+e+c),  beta = (a+b+d+e, a+c+d+f, b+c+e+f),
+//   P = prod over the four triads (x y z) of (x+y-z)! (x-y+z)! (-x+y+z)! / (x+y+z+1)!.
+//
+// Evaluation, designed so that the result is within a few ulp of the exact value:
+//  * The common factor sqrt(P) * T0 (T0 = |first term|) is an exact rational square root.
+//    Its prime factorisation is assembled from a table of prime exponents of n! (Legendre's
+//    formula), and the product prod_p sqrt(p)^{E_p} is formed in double-double arithmetic
+//    with a separate binary exponent, so no factorial is ever rounded.
+//  * The remaining sum is 1 + r_0 + r_0 r_1 + ... with exact integer ratios
+//    r_t = -(t+2) prod_j (beta_j - t) / prod_i (t + 1 - alpha_i); the ratios and the running
+//    products and sum are carried in double-double, which removes the effect of the
+//    alternating-sign cancellation at the spins handled here.
+// Double-double primitives follow Dekker (1971) and Knuth (TAOCP vol. 2, 4.2.2).
+#include "eprl_internal.hpp"
+
+namespace eprl {
+
+namespace {
+
+struct dd {
+  double hi, lo;
+};
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+
+__device__ __forceinline__ dd fast_two_sum(double a, double b) {
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+__device__ __forceinline__ dd dd_mul(dd a, dd b) {
+  double p = a.hi * b.hi;
+  double e = __builtin_fma(a.hi, b.hi, -p);
+  e += a.hi * b.lo + a.lo * b.hi;
+  return fast_two_sum(p, e);
+}
+
+// Quotient of two exactly representable integers as a double-double.
+__device__ __forceinline__ dd dd_ratio(double num, double den) {
+  double q = num / den;
+  double r = __builtin_fma(-q, den, num);  // exact remainder
+  return fast_two_sum(q, r / den);
+}
+
+// Double-double with a separate power-of-two exponent: value = (hi + lo) * 2^e.
+struct dde {
+  double hi, lo;
+  int e;
+};
+
+__device__ __forceinline__ void normalise(dde &v) {
+  int k;
+  double h = __builtin_frexp(v.hi, &k);
+  v.lo = __builtin_ldexp(v.lo, -k);
+  v.hi = h;
+  v.e += k;
+}
+
+__device__ __forceinline__ dde dde_mul(dde a, dd b) {
+  dd m = dd_mul({a.hi, a.lo}, b);
+  dde r{m.hi, m.lo, a.e};
+  normalise(r);
+  return r;
+}
+
+__device__ __forceinline__ dde dde_mul(dde a, dde b) {
+  dd m = dd_mul({a.hi, a.lo}, {b.hi, b.lo});
+  dde r{m.hi, m.lo, a.e + b.e};
+  normalise(r);
+  return r;
+}
+
+// sqrt(q) of a small integer q as a double-double.
+__device__ __forceinline__ dd dd_sqrt_int(double q) {
+  double s = __builtin_sqrt(q);
+  double r = __builtin_fma(-s, s, q);
+  return fast_two_sum(s, r / (2.0 * s));
+}
+
+// base^n, n >= 0, by binary powering.
+__device__ dde dde_pow(dd base, int n) {
+  dde result{1.0, 0.0, 0};
+  dde b{base.hi, base.lo, 0};
+  normalise(b);
+  while (n > 0) {
+    if (n & 1) result = dde_mul(result, b);
+    n >>= 1;
+    if (n) b = dde_mul(b, b);
+  }
+  return result;
+}
+
+__device__ __forceinline__ bool triad_ok(int a, int b, int c) {
+  return ((a + b + c) & 1) == 0 && c >= (a > b ? a - b : b - a) && c <= a + b;
+}
+
+// {a b c; d e f}, all arguments in two-units.  `fexp` holds v_p(n!) for n <= fact_max.
+__device__ double sixj_device(int a, int b, int c, int d, int e, int f, const uint16_t *fexp,
+                              const int *primes, int nprime) {
+  if (!(triad_ok(a, b, c) && triad_ok(a, e, f) && triad_ok(d, b, f) && triad_ok(d, e, c)))
+    return 0.0;
+  const int al[4] = {(a + b + c) / 2, (a + e + f) / 2, (d + b + f) / 2, (d + e + c) / 2};
+  const int be[3] = {(a + b + d + e) / 2, (a + c + d + f) / 2, (b + c + e + f) / 2};
+  int tmin = al[0], tmax = be[0];
+  for (int q = 1; q < 4; ++q) tmin = al[q] > tmin ? al[q] : tmin;
+  for (int q = 1; q < 3; ++q) tmax = be[q] < tmax ? be[q] : tmax;
+  // Factorial arguments with their exponent in P * T0^2.
+  const int tri[4][3] = {{a, b, c}, {a, e, f}, {d, b, f}, {d, e, c}};
+  int arg[21], coef[21];
+  int na = 0, top = tmin + 1;
+  for (int q = 0; q < 4; ++q) {
+    const int x = tri[q][0], y = tri[q][1], z = tri[q][2];
+    arg[na] = (x + y - z) / 2; coef[na++] = 1;
+    arg[na] = (x - y + z) / 2; coef[na++] = 1;
+    arg[na] = (-x + y + z) / 2; coef[na++] = 1;
+    arg[na] = (x + y + z) / 2 + 1; coef[na++] = -1;
+    if ((x + y + z) / 2 + 1 > top) top = (x + y + z) / 2 + 1;
+  }
+  arg[na] = tmin + 1; coef[na++] = 2;
+  for (int q = 0; q < 4; ++q) { arg[na] = tmin - al[q]; coef[na++] = -2; }
+  for (int q = 0; q < 3; ++q) { arg[na] = be[q] - tmin; coef[na++] = -2; }
+  // prod_p sqrt(p)^{E_p}: numerator and denominator powers kept apart.
+  dde num{0.5, 0.0, 1}, den{0.5, 0.0, 1};
+  for (int ip = 0; ip < nprime; ++ip) {
+    const int pr = primes[ip];
+    if (pr > top) break;
+    int E = 0;
+    for (int q = 0; q < na; ++q) E += coef[q] * (int)fexp[arg[q] * nprime + ip];
+    if (E == 0) continue;
+    dd sp = dd_sqrt_int((double)pr);
+    if (E > 0)
+      num = dde_mul(num, dde_pow(sp, E));
+    else
+      den = dde_mul(den, dde_pow(sp, -E));
+  }
+  // Series in double-double.
+  dd rho{1.0, 0.0}, sum{1.0, 0.0};
+  for (int t = tmin; t < tmax; ++t) {
+    double nu = -(double)(t + 2) * (double)(be[0] - t) * (double)(be[1] - t) * (double)(be[2] - t);
+    double de = (double)(t + 1 - al[0]) * (double)(t + 1 - al[1]) * (double)(t + 1 - al[2]) *
+                (double)(t + 1 - al[3]);
+    rho = dd_mul(rho, dd_ratio(nu, de));
+    sum = dd_add(sum, rho);
+  }
+  // value = (-1)^tmin * num / den * sum
+  dd q;
+  {
+    // num / den in double-double: q = num.hi / den.hi, then one correction step.
+    double qh = num.hi / den.hi;
+    dd prod = dd_mul({qh, 0.0}, {den.hi, den.lo});
+    dd diff = dd_add({num.hi, num.lo}, {-prod.hi, -prod.lo});
+    q = fast_two_sum(qh, diff.hi / den.hi);
+  }
+  dd v = dd_mul(q, sum);
+  double r = __builtin_ldexp(v.hi + v.lo, num.e - den.e);
+  return (tmin & 1) ? -r : r;
+}
+
+__global__ void fexp_kernel(uint16_t *fexp, int fact_max, const int *primes, int nprime) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (fact_max + 1) * nprime) return;
+  const int n = idx / nprime, p = primes[idx % nprime];
+  // Legendre: v_p(n!) = sum_k floor(n / p^k)
+  int v = 0;
+  for (long long pk = p; pk <= n; pk *= p) v += (int)(n / pk);
+  fexp[idx] = (uint16_t)v;
+}
+
+// One thread per table entry.  Table t (0..4), its linear index decomposed row-major.
+__global__ void sixj_table_kernel(TableParams tp, int64_t total) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  int t = 0;
+  while (t < 4 && g >= tp.toff[t + 1]) ++t;
+  int64_t idx = g - tp.toff[t];
+  const int nd = tp.nd;
+  const int *J = tp.two_j;
+  const int NX = tp.NX;
+  int64_t size;
+  switch (t) {
+    case 0: size = (int64_t)nd * tp.i1_n * tp.K_n[3] * NX; break;
+    case 1: size = (int64_t)nd * nd * tp.K_n[3] * tp.K_n[2] * NX; break;
+    case 2: size = (int64_t)nd * nd * nd * tp.K_n[2] * tp.K_n[1] * NX; break;
+    case 3: size = (int64_t)nd * nd * tp.K_n[1] * tp.K_n[0] * NX; break;
+    default: size = (int64_t)nd * tp.K_n[0] * tp.i1_n * NX; break;
+  }
+  if (idx >= size) return;  // alignment padding between tables
+  const int x = tp.X_lo2 + 2 * (int)(idx % NX);
+  int64_t r = idx / NX;
+  int args[6];
+  if (t == 0) {  // T1[o25][i1][k5][x] = {i1 l25 x; k5 j14 j15}
+    int k5 = tp.K_lo2[3] + 2 * (int)(r % tp.K_n[3]); r /= tp.K_n[3];
+    int i1 = tp.i1_lo2 + 2 * (int)(r % tp.i1_n); r /= tp.i1_n;
+    int l25 = J[L25] + 2 * (int)r;
+    int a6[6] = {i1, l25, x, k5, J[L14], J[L15]};
+    for (int q = 0; q < 6; ++q) args[q] = a6[q];
+  } else if (t == 1) {  // T2[o35][o45][k5][k4][x] = {j14 k5 x; l35 k4 l45}
+    int k4 = tp.K_lo2[2] + 2 * (int)(r % tp.K_n[2]); r /= tp.K_n[2];
+    int k5 = tp.K_lo2[3] + 2 * (int)(r % tp.K_n[3]); r /= tp.K_n[3];
+    int l45 = J[L45] + 2 * (int)(r % nd); r /= nd;
+    int l35 = J[L35] + 2 * (int)r;
+    int a6[6] = {J[L14], k5, x, l35, k4, l45};
+    for (int q = 0; q < 6; ++q) args[q] = a6[q];
+  } else if (t == 2) {  // T3[o24][o34][o35][k4][k3][x] = {k4 l35 x; k3 l24 l34}
+    int k3 = tp.K_lo2[1] + 2 * (int)(r % tp.K_n[1]); r /= tp.K_n[1];
+    int k4 = tp.K_lo2[2] + 2 * (int)(r % tp.K_n[2]); r /= tp.K_n[2];
+    int l35 = J[L35] + 2 * (int)(r % nd); r /= nd;
+    int l34 = J[L34] + 2 * (int)(r % nd); r /= nd;
+    int l24 = J[L24] + 2 * (int)r;
+    int a6[6] = {k4, l35, x, k3, l24, l34};
+    for (int q = 0; q < 6; ++q) args[q] = a6[q];
+  } else if (t == 3) {  // T4[o23][o24][k3][k2][x] = {l24 k3 x; j13 k2 l23}
+    int k2 = tp.K_lo2[0] + 2 * (int)(r % tp.K_n[0]); r /= tp.K_n[0];
+    int k3 = tp.K_lo2[1] + 2 * (int)(r % tp.K_n[1]); r /= tp.K_n[1];
+    int l24 = J[L24] + 2 * (int)(r % nd); r /= nd;
+    int l23 = J[L23] + 2 * (int)r;
+    int a6[6] = {l24, k3, x, J[L13], k2, l23};
+    for (int q = 0; q < 6; ++q) args[q] = a6[q];
+  } else {  // T5[o25][k2][i1][x] = {k2 j13 x; i1 l25 j12}
+    int i1 = tp.i1_lo2 + 2 * (int)(r % tp.i1_n); r /= tp.i1_n;
+    int k2 = tp.K_lo2[0] + 2 * (int)(r % tp.K_n[0]); r /= tp.K_n[0];
+    int l25 = J[L25] + 2 * (int)r;
+    int a6[6] = {k2, J[L13], x, i1, l25, J[L12]};
+    for (int q = 0; q < 6; ++q) args[q] = a6[q];
+  }
+  tp.tables[g] = sixj_device(args[0], args[1], args[2], args[3], args[4], args[5], tp.fexp,
+                             tp.primes, tp.nprime);
+}
+
+__global__ void sixj_batch_kernel(const int *args, int n, double *out, const uint16_t *fexp,
+                                  const int *primes, int nprime, int fact_max) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int *a = args + 6 * i;
+  // Arguments beyond the factorial table are rejected by the host; guard anyway.
+  int s = 0;
+  for (int q = 0; q < 6; ++q) s = a[q] > s ? a[q] : s;
+  if (2 * s + 2 > fact_max) {
+    out[i] = __builtin_nan("");
+    return;
+  }
+  out[i] = sixj_device(a[0], a[1], a[2], a[3], a[4], a[5], fexp, primes, nprime);
+}
+
+}  // namespace
+
+hipError_t launch_fexp_table(uint16_t *fexp, int fact_max, const int *primes, int nprime,
+                             hipStream_t s) {
+  int total = (fact_max + 1) * nprime;
+  fexp_kernel<<<(total + 255) / 256, 256, 0, s>>>(fexp, fact_max, primes, nprime);
+  return hipGetLastError();
+}
+
+hipError_t launch_sixj_tables(const TableParams &tp, int64_t total, hipStream_t s) {
+  int64_t blocks = (total + 255) / 256;
+  sixj_table_kernel<<<(unsigned)blocks, 256, 0, s>>>(tp, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_sixj_batch(const int *args, int n, double *out, const uint16_t *fexp,
+                             const int *primes, int nprime, int fact_max, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  sixj_batch_kernel<<<(n + 255) / 256, 256, 0, s>>>(args, n, out, fexp, primes, nprime,
+                                                    fact_max);
+  return hipGetLastError();
+}
+
+}  // namespace eprl

@@ -1,0 +1,255 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars:
+* 6j symbols: every device value within 4 ulp of the exactly rounded oracle value (zeros exact).
+* {15j} tensors W of single shells and vertex tensors A: normwise relative error
+  max|GPU - oracle| / max|oracle| <= 1e-10 (the parity bar of the method in FP64); typical
+  observed values are ~1e-15.
+* Contraction and gradients: relative error <= 1e-10 against the oracle's FP64 values;
+  adjoint against central finite differences within 2e-8.
+Shell-range partial sums must add up to the full tensor and repeated calls must be bitwise
+identical (fixed-order reductions).
+"""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import ranges as R
+from oracle import vertex as V
+from oracle import contract as C
+from oracle.fifteenj import fifteenj_block
+from oracle.wigner import sixj, triad
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2107_13952_amd as lib
+    return lib
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    return torch
+
+
+def normwise(a, ref):
+    ref = np.asarray(ref)
+    scale = np.abs(ref).max()
+    return np.abs(np.asarray(a) - ref).max() / (scale if scale > 0 else 1.0)
+
+
+def boosters_for(torch, two_j, dl, seed):
+    b = workloads.synthetic_boosters(seed, R.block_shapes(two_j, dl))
+    return b, torch.from_numpy(b).cuda()
+
+
+# ------------------------------------------------------------------ 6j symbols
+
+def test_sixj_device_vs_exact(lib, torch):
+    rng = random.Random(42)
+    args = []
+    while len(args) < 3000:
+        s = [rng.randint(0, 40) for _ in range(6)]
+        a, b, c, d, e, f = s
+        if triad(a, b, c) and triad(a, e, f) and triad(d, b, f) and triad(d, e, c):
+            args.append(s)
+    # a few large spins and non-admissible ones
+    args += [[120, 118, 60, 80, 90, 100], [200, 200, 200, 200, 200, 200], [2, 2, 2, 2, 2, 9]]
+    note(f"sixj_batch: {len(args)} symbols")
+    out = lib.sixj_batch(np.array(args)).cpu().numpy()
+    ref = np.array([sixj(*s) for s in args])
+    zero = ref == 0.0
+    assert np.all(out[zero] == 0.0)
+    ulp = np.abs(out[~zero] - ref[~zero]) / np.spacing(np.abs(ref[~zero]))
+    assert ulp.max() <= 4, ulp.max()
+
+
+# ------------------------------------------------------------------ {15j} of single shells
+
+SHELL_CASES = [([2] * 10, 3), ([2, 3, 2, 1, 3, 2, 3, 1, 1, 3], 2), ([6] * 10, 8),
+               ([13, 10, 11, 12, 10, 14, 11, 13, 13, 10], 2)]
+
+
+@pytest.mark.parametrize("two_j,dl", SHELL_CASES)
+def test_shell_fifteenj(lib, torch, two_j, dl):
+    shells = R.live_shells(two_j, dl) if dl <= 3 else None
+    rng = random.Random(7)
+    nd = dl + 1
+    picks = []
+    while len(picks) < 6:
+        s = tuple(rng.randrange(nd) for _ in range(6))
+        if R.shell_is_live(two_j, s):
+            picks.append(s)
+    if shells:
+        picks += [shells[0], shells[-1]]
+    for s in picks:
+        idx = 0
+        for o in s:
+            idx = idx * nd + o
+        note(f"shell_fifteenj {two_j} dl={dl} shell={s}")
+        w = lib.shell_fifteenj(two_j, dl, idx).cpu().numpy()
+        two_l = R.shell_spins(two_j, s)
+        kr = [R.virtual_range(two_l, e) for e in range(2, 6)]
+        ref = fifteenj_block(R.boundary_ranges(two_j)[0], kr, two_l)
+        assert w.shape == ref.shape
+        assert normwise(w, ref) <= 1e-13, (s, normwise(w, ref))
+
+
+# ------------------------------------------------------------------ vertex tensors
+
+SMALL = [([2] * 10, 3, 1001),                                  # j = 1, dl = 3 (cfg1 shape)
+         ([2, 3, 2, 1, 3, 2, 3, 1, 1, 3], 2, 11),               # half-integer, irregular
+         ([1] * 10, 2, 12),                                     # all spins 1/2
+         ([4, 1, 1, 4, 4, 3, 3, 1, 4, 1], 3, 13),               # ragged k ranges
+         ([6] * 10, 1, 14),                                     # j = 3 (cfg2 spins), dl = 1
+         ([13, 10, 11, 12, 10, 14, 11, 13, 13, 10], 1, 15),     # dims 11 (wide tile path)
+         ([8] * 10, 0, 16)]                                     # Delta s = 0
+
+
+@pytest.mark.parametrize("two_j,dl,seed", SMALL)
+def test_vertex_tensor_small(lib, torch, two_j, dl, seed):
+    b, bd = boosters_for(torch, two_j, dl, seed)
+    note(f"vertex_tensor {two_j} dl={dl}")
+    a = lib.vertex_tensor(two_j, dl, 1.2, bd).cpu().numpy()
+    ref = V.vertex_tensor(two_j, dl, b)
+    err = normwise(a, ref)
+    note(f"  normwise error {err:.3e}")
+    assert err <= TOL
+
+
+def test_bf_limit_identity_boosters(lib, torch):
+    two_j = [2, 3, 2, 1, 3, 2, 3, 1, 1, 3]
+    shapes, offsets = R.booster_layout(two_j, 0)
+    parts = []
+    for e in range(2, 6):
+        rows, cols, klo = shapes[(e, 0)]
+        parts.append((np.eye(rows) / (klo + 2 * np.arange(cols) + 1.0)[None, :]).ravel())
+    b = np.concatenate(parts)
+    note("BF limit")
+    a = lib.vertex_tensor(two_j, 0, 1.0, torch.from_numpy(b).cuda()).cpu().numpy()
+    assert normwise(a, V.bf_vertex(two_j)) <= 1e-13
+
+
+def test_range_additivity_and_determinism(lib, torch):
+    two_j, dl = [6] * 10, 2
+    b, bd = boosters_for(torch, two_j, dl, 21)
+    n = (dl + 1) ** 6
+    note("range additivity")
+    full = lib.vertex_tensor(two_j, dl, 1.2, bd)
+    again = lib.vertex_tensor(two_j, dl, 1.2, bd)
+    assert torch.equal(full, again)
+    part = lib.vertex_tensor_range(two_j, dl, 1.2, bd, 0, 300)
+    lib.vertex_tensor_range(two_j, dl, 1.2, bd, 300, n, accumulate=True, out=part)
+    assert normwise(part.cpu().numpy(), full.cpu().numpy()) <= 1e-14
+    ref = V.vertex_tensor(two_j, dl, b, shells=R.all_shells(dl)[:300])
+    mid = lib.vertex_tensor_range(two_j, dl, 1.2, bd, 0, 300).cpu().numpy()
+    assert normwise(mid, ref) <= TOL
+
+
+def test_cfg2_full_size_sampled_range(lib, torch):
+    """j = 3, dl = 8 at full size: a contiguous block of shells against the oracle, and the
+    full tensor checked for determinism and additivity of two halves."""
+    cfg = workloads.CFG2
+    two_j, dl = cfg["two_j"], cfg["dl"]
+    b, bd = boosters_for(torch, two_j, dl, cfg["booster_seed"])
+    n = (dl + 1) ** 6
+    s0, s1 = 250000, 251500
+    note("cfg2 sampled range")
+    part = lib.vertex_tensor_range(two_j, dl, 1.2, bd, s0, s1).cpu().numpy()
+    ref = V.vertex_tensor(two_j, dl, b, shells=R.all_shells(dl)[s0:s1])
+    err = normwise(part, ref)
+    note(f"  normwise error {err:.3e}")
+    assert err <= TOL
+    note("cfg2 full tensor")
+    full = lib.vertex_tensor(two_j, dl, 1.2, bd)
+    again = lib.vertex_tensor(two_j, dl, 1.2, bd)
+    assert torch.equal(full, again)
+    halves = lib.vertex_tensor_range(two_j, dl, 1.2, bd, 0, n // 2)
+    lib.vertex_tensor_range(two_j, dl, 1.2, bd, n // 2, n, accumulate=True, out=halves)
+    assert normwise(halves.cpu().numpy(), full.cpu().numpy()) <= 1e-13
+
+
+def test_batched_equals_plain(lib, torch):
+    configs = workloads.cfg3_batch()[:6]
+    configs = [(tj, min(dl, 2)) for tj, dl in configs]
+    bs = [boosters_for(torch, tj, dl, 3000 + c) for c, (tj, dl) in enumerate(configs)]
+    note("batched vs plain")
+    outs = lib.vertex_tensor_batched(configs, 1.2, [bd for _, bd in bs])
+    for (tj, dl), (b, bd), a in zip(configs, bs, outs):
+        plain = lib.vertex_tensor(tj, dl, 1.2, bd)
+        assert torch.equal(a, plain)
+        assert normwise(a.cpu().numpy(), V.vertex_tensor(tj, dl, b)) <= TOL
+
+
+# ------------------------------------------------------------------ contraction and adjoint
+
+def test_contract_and_adjoint(lib, torch):
+    two_j, dl = [4, 1, 2, 3, 1, 3, 2, 4, 4, 1], 2
+    b, bd = boosters_for(torch, two_j, dl, 31)
+    note("contract + adjoint")
+    A = lib.vertex_tensor(two_j, dl, 1.2, bd)
+    a = A.cpu().numpy()
+    psis = workloads.boundary_vectors(31, a.shape)
+    pd = [torch.from_numpy(p).cuda() for p in psis]
+    F = complex(lib.contract_boundary(A, pd).cpu().item())
+    Fref = C.contract_boundary(V.vertex_tensor(two_j, dl, b), psis)
+    assert abs(F - Fref) <= TOL * max(1.0, abs(Fref))
+    g = 0.3 - 0.7j
+    gpsi, gb = lib.contract_boundary_adjoint(two_j, dl, bd, A, pd, g)
+    ref_psi = C.grad_psi(a, psis)
+    for q in range(5):
+        assert normwise(gpsi[q].cpu().numpy(), g * ref_psi[q]) <= TOL
+    ref_b = C.grad_boosters(two_j, dl, b, psis)
+    assert normwise(gb.cpu().numpy(), g * ref_b) <= TOL
+
+
+def test_autograd_against_finite_differences(lib, torch):
+    from paper_2107_13952_amd.autograd import vertex_contract
+    two_j, dl = [2, 3, 2, 1, 3, 2, 3, 1, 1, 3], 1
+    b, _ = boosters_for(torch, two_j, dl, 41)
+    dims = [n for _, n in R.boundary_ranges(two_j)]
+    psis = workloads.boundary_vectors(41, dims)
+    bt = torch.from_numpy(b).cuda().requires_grad_(True)
+    pts = [torch.from_numpy(p).cuda().requires_grad_(True) for p in psis]
+    note("autograd")
+    F = vertex_contract(two_j, dl, 1.2, bt, pts)
+    loss = (F * (0.4 + 0.9j)).real
+    loss.backward()
+    h = 1e-6
+
+    def L(bv, pv):
+        A = V.vertex_tensor(two_j, dl, bv)
+        return (C.contract_boundary(A, pv) * (0.4 + 0.9j)).real
+
+    rng = np.random.default_rng(0)
+    gb = bt.grad.cpu().numpy()
+    for n in rng.choice(b.size, size=12, replace=False):
+        up, dn = b.copy(), b.copy()
+        up[n] += h
+        dn[n] -= h
+        fd = (L(up, psis) - L(dn, psis)) / (2 * h)
+        assert abs(fd - gb[n]) <= 2e-8 * max(1.0, abs(fd))
+    for q in range(5):
+        gq = pts[q].grad.cpu().numpy()
+        for n in range(dims[q]):
+            for delta in (h, 1j * h):
+                up = [p.copy() for p in psis]
+                dn = [p.copy() for p in psis]
+                up[q][n] += delta
+                dn[q][n] -= delta
+                fd = (L(b, up) - L(b, dn)) / (2 * h)
+                got = gq[n].real if delta == h else gq[n].imag
+                assert abs(fd - got) <= 2e-8 * max(1.0, abs(fd))
