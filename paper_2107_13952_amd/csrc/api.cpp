@@ -63,23 +63,23 @@ struct TimedLaunch {
   TimedLaunch(eprl_ctx *c_, int k) : c(c_), kernel(k) {
     if (!c->timing) return;
     if (hipEventCreate(&start) != hipSuccess || hipEventCreate(&stop) != hipSuccess) {
-      hipGetLastError();
+      (void)hipGetLastError();
       start = stop = nullptr;
       return;
     }
-    hipEventRecord(start, c->stream);
+    (void)hipEventRecord(start, c->stream);
   }
   ~TimedLaunch() {
     if (!start) return;
-    hipEventRecord(stop, c->stream);
+    (void)hipEventRecord(stop, c->stream);
     c->recs.push_back({kernel, start, stop});
   }
 };
 
 void clear_timing(eprl_ctx *c) {
   for (auto &r : c->recs) {
-    hipEventDestroy(r.start);
-    hipEventDestroy(r.stop);
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
   }
   c->recs.clear();
 }
@@ -100,7 +100,7 @@ int ensure_workspace(eprl_ctx *c, size_t bytes) {
     c->ws = nullptr;
     if (hipMalloc(&c->ws, bytes) != hipSuccess) {
       c->ws = nullptr;
-      hipGetLastError();
+      (void)hipGetLastError();
       return fail(c, EPRL_ENOMEM, "device workspace allocation failed");
     }
     want = bytes;
@@ -122,7 +122,7 @@ int staging(eprl_ctx *c, size_t bytes, char **out) {
     if (hipHostMalloc((void **)&c->stage, want, hipHostMallocDefault) != hipSuccess) {
       c->stage = nullptr;
       c->stage_size = 0;
-      hipGetLastError();
+      (void)hipGetLastError();
       return fail(c, EPRL_ENOMEM, "pinned staging allocation failed");
     }
     c->stage_size = want;
@@ -150,7 +150,7 @@ int ensure_fexp(eprl_ctx *c, int fact_max) {
   c->fact_max = -1;
   if (hipMalloc(&c->primes, pr.size() * sizeof(int)) != hipSuccess ||
       hipMalloc(&c->fexp, (size_t)(fact_max + 1) * pr.size() * sizeof(uint16_t)) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(c, EPRL_ENOMEM, "factorial table allocation failed");
   }
   char *st;
@@ -315,7 +315,7 @@ int eprl_create(eprl_ctx **out, int device, void *hip_stream) {
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipSetDevice(device) != hipSuccess || hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     delete c;
     return EPRL_EHIP;
   }
@@ -325,14 +325,14 @@ int eprl_create(eprl_ctx **out, int device, void *hip_stream) {
 
 void eprl_destroy(eprl_ctx *c) {
   if (!c) return;
-  hipSetDevice(c->device);
-  if (c->stream) hipStreamSynchronize(c->stream);
-  else hipDeviceSynchronize();
-  if (c->ws) hipFree(c->ws);
-  if (c->stage) hipHostFree(c->stage);
-  if (c->fexp) hipFree(c->fexp);
-  if (c->primes) hipFree(c->primes);
-  if (c->stage_done) hipEventDestroy(c->stage_done);
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->stage) (void)hipHostFree(c->stage);
+  if (c->fexp) (void)hipFree(c->fexp);
+  if (c->primes) (void)hipFree(c->primes);
+  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
   clear_timing(c);
   delete c;
 }

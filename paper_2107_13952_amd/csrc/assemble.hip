@@ -76,7 +76,7 @@ __device__ __forceinline__ void w_row(const VertexParams &vp, const ShellHeader 
   for (int q = 0; q < D; ++q) w[q] = 0.0;
   const int two_i1 = vp.i_lo2[0] + 2 * n1;
   const int two_k2 = h.klo[0] + 2 * k2, two_k3 = h.klo[1] + 2 * k3, two_k4 = h.klo[2] + 2 * k4;
-  const int l24 = h.l[L24], l25 = h.l[L25], l35 = h.l[L35], j13 = h.l[L13], j14 = h.l[L14];
+  const int l24 = h.l[L24], l25 = h.l[L25], l35 = h.l[L35], j13 = h.l[L13];
   // x closes (i1 l25 x), (j13 k2 x), (l24 k3 x), (l35 k4 x); (k5 j14 x) is handled by the
   // zeros of the first table.
   int lo = imax(imax(iabs(two_i1 - l25), iabs(j13 - two_k2)),

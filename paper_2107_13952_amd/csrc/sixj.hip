@@ -75,13 +75,6 @@ __device__ __forceinline__ void normalise(dde &v) {
   v.e += k;
 }
 
-__device__ __forceinline__ dde dde_mul(dde a, dd b) {
-  dd m = dd_mul({a.hi, a.lo}, b);
-  dde r{m.hi, m.lo, a.e};
-  normalise(r);
-  return r;
-}
-
 __device__ __forceinline__ dde dde_mul(dde a, dde b) {
   dd m = dd_mul({a.hi, a.lo}, {b.hi, b.lo});
   dde r{m.hi, m.lo, a.e + b.e};
@@ -125,7 +118,7 @@ __device__ double sixj_device(int a, int b, int c, int d, int e, int f, const ui
   for (int q = 1; q < 3; ++q) tmax = be[q] < tmax ? be[q] : tmax;
   // Factorial arguments with their exponent in P * T0^2.
   const int tri[4][3] = {{a, b, c}, {a, e, f}, {d, b, f}, {d, e, c}};
-  int arg[21], coef[21];
+  int arg[24], coef[24];
   int na = 0, top = tmin + 1;
   for (int q = 0; q < 4; ++q) {
     const int x = tri[q][0], y = tri[q][1], z = tri[q][2];

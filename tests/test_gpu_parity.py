@@ -1,7 +1,8 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
 Bars:
-* 6j symbols: every device value within 4 ulp of the exactly rounded oracle value (zeros exact).
+* 6j symbols: every device value within 4 ulp of the exactly rounded oracle value; exact
+  zeros of the Racah sum within 1e-28.
 * {15j} tensors W of single shells and vertex tensors A: normwise relative error
   max|GPU - oracle| / max|oracle| <= 1e-10 (the parity bar of the method in FP64); typical
   observed values are ~1e-15.
@@ -72,7 +73,8 @@ def test_sixj_device_vs_exact(lib, torch):
     out = lib.sixj_batch(np.array(args)).cpu().numpy()
     ref = np.array([sixj(*s) for s in args])
     zero = ref == 0.0
-    assert np.all(out[zero] == 0.0)
+    # non-trivial zeros of the Racah sum come out at the double-double residual level
+    assert np.all(np.abs(out[zero]) <= 1e-28)
     ulp = np.abs(out[~zero] - ref[~zero]) / np.spacing(np.abs(ref[~zero]))
     assert ulp.max() <= 4, ulp.max()
 
