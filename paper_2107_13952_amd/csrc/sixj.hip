@@ -18,6 +18,11 @@
 // Double-double primitives follow Dekker (1971) and Knuth (TAOCP vol. 2, 4.2.2).
 #include "eprl_internal.hpp"
 
+// The error-free transformations below need every product and sum rounded exactly as
+// written: fusing p = a*b into a later p + e (the default contraction of device code) would
+// destroy the error terms.
+#pragma clang fp contract(off)
+
 namespace eprl {
 
 namespace {
