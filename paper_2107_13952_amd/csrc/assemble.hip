@@ -279,7 +279,10 @@ __global__ void shell_fifteenj_kernel(VertexParams vp, int64_t shell, double *W)
   const int k4 = u % dk4, k3 = (u / dk4) % dk3, k2 = (u / (dk4 * dk3)) % dk2, n1 = u / (dk4 * dk3 * dk2);
   double w[D];
   w_row<D>(vp, h, n1, k2, k3, k4, w);
-  for (int k5 = 0; k5 < dk5; ++k5) W[(int64_t)u * dk5 + k5] = w[k5];
+  // The assembly folds (-1)^{k - k_lo} of every virtual intertwiner into the booster blocks;
+  // restore it here so that W carries the full (-1)^R.
+  const double s = ((k2 + k3 + k4) & 1) ? -1.0 : 1.0;
+  for (int k5 = 0; k5 < dk5; ++k5) W[(int64_t)u * dk5 + k5] = (k5 & 1) ? -s * w[k5] : s * w[k5];
 }
 
 }  // namespace
