@@ -100,6 +100,10 @@ def cpu_baseline(two_j, dl, boosters_np, nshell_sample):
                       f"{terms:.3g} terms in {dt:.1f} s, one thread"}
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +135,7 @@ def main():
     xterms = sampled_xterms(two_j, dl, dims, ilo, kd)
     alg_flops = 2.0 * macs + 6.0 * xterms
 
+    progress(f"workload two_j={two_j} dl={dl}: {live} live shells, {terms:.3g} terms")
     out = torch.empty(dims, dtype=torch.float64, device=dev)
     for _ in range(args.warmup):
         lib.vertex_tensor(two_j, dl, 1.2, b, out=out)
@@ -150,6 +155,7 @@ def main():
     red_ms, red_n = lib.timing_read("reduce")
     lib.timing_enable(False)
     asm_avg = asm_ms / max(asm_n, 1)
+    progress(f"timed {args.steps} steps: {ms:.3f} ms/step, assembly kernel {asm_avg:.3f} ms")
     achieved = alg_flops / (asm_avg * 1e-3) / 1e12
 
     result = {
@@ -186,8 +192,10 @@ def main():
                   for e in range(4) for t in range((d + 1) ** 3)]
             bl.append(torch.from_numpy(workloads.synthetic_boosters(1003 + 1000 + c, sh)).to(dev))
         bterms = sum(lib.count_terms(tj, d)[1] for tj, d in configs)
+        progress(f"batched workload: {len(configs)} configurations, {bterms:.3g} terms")
         outs = lib.vertex_tensor_batched(configs, 1.2, bl)
         torch.cuda.synchronize()
+        progress("batched warm-up done")
         t0 = time.perf_counter()
         lib.vertex_tensor_batched(configs, 1.2, bl, outs)
         torch.cuda.synchronize()
@@ -197,10 +205,12 @@ def main():
             lib.vertex_tensor(tj, d, 1.2, bb, out=a)
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
+        progress(f"batched {t_batched:.2f} s, plain {t_plain:.2f} s")
         result["batched"] = {"workload": "64 seeded configurations, j in 1/2..6, dl in 3..10",
                              "terms": bterms, "batched_terms_per_s": bterms / t_batched,
                              "plain_terms_per_s": bterms / t_plain}
     if args.cpu_shells > 0:
+        progress(f"cpu baseline: oracle on {args.cpu_shells} shells")
         result["cpu_baseline"] = cpu_baseline(two_j, dl, b_np, args.cpu_shells)
     print(json.dumps(result), flush=True)
 
