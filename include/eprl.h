@@ -67,6 +67,20 @@ const char *eprl_last_error(const eprl_ctx *ctx);
 /* Change the stream subsequent calls are enqueued on. */
 int eprl_set_stream(eprl_ctx *ctx, void *hip_stream);
 
+/* How eprl_vertex_tensor evaluates the shell sum (both give the same tensor up to rounding):
+ *  EPRL_ALGO_SHELL  the framed algorithm of Sec. 3.1 literally: per shell the {15j} tensor W
+ *                   and the four booster mode products k5, k4, k3, k2, accumulated over shells;
+ *  EPRL_ALGO_RING   the same sum regrouped by linearity: for each x of eq. (15j) and each
+ *                   (l24, l25, l34, l35) the l45 and l23 sums are taken inside the two halves
+ *                   of the closed chain of 6j and booster matrices, then contracted over k4 and
+ *                   k3 with FP64 matrix-core tiles.  Needs every i and k range <= 8 and is used
+ *                   for full-range calls only;
+ *  EPRL_ALGO_AUTO   (default) RING where it applies, SHELL otherwise. */
+#define EPRL_ALGO_AUTO 0
+#define EPRL_ALGO_SHELL 1
+#define EPRL_ALGO_RING 2
+int eprl_set_algorithm(eprl_ctx *ctx, int algo);
+
 /* Host-only (no GPU use).  Ranges of the vertex tensor (eq. (vertex-ampl)) and the packed
  * booster layout described above.
  *   dims_i[5]        out: dim(i1) .. dim(i5)
@@ -80,6 +94,14 @@ int eprl_layout(const int two_j[10], int dl, int dims_i[5], int two_ilo[5],
 /* Host-only.  Number of live shells (every k_e range non-empty) among the (dl+1)^6, and the
  * number of {15j} x booster terms sum_{live shells} dim(i1) prod_e dim(k_e). */
 int eprl_count_terms(const int two_j[10], int dl, int64_t *live_shells, double *terms);
+
+/* Host-only.  Exact work of one vertex tensor, for rooflines:
+ *   out[0] = {15j} x booster terms (as eprl_count_terms);
+ *   out[1] = FP64 flops of the per-shell order: 2 x (multiply-adds of the four mode products)
+ *            + 6 per (term, allowed x) for the {15j} sums;
+ *   out[2] = useful FP64 flops of the factorised order (active index ranges only);
+ *   out[3] = FP64 flops its matrix-core tiles execute (16x16x4 tiles, padding included). */
+int eprl_count_work(const int two_j[10], int dl, double out[4]);
 
 /* The vertex tensor of eq. (vertex-ampl), computed by the framed algorithm of Sec. 3.1:
  * 6j tables (step 4), then per shell the {15j} tensor W (6(i)), the booster sub-matrices
@@ -136,8 +158,8 @@ int eprl_shell_fifteenj(eprl_ctx *ctx, const int two_j[10], int dl, int64_t shel
                         int kdims[4], double *W, int64_t capacity);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around each launch.
- * kernel ids: 0 = 6j table builder, 1 = vertex assembly, 2 = shell-sum reduction,
- * 3 = adjoint shell kernel.  eprl_timing_enable(ctx, 1) starts recording (clearing earlier
+ * kernel ids: 0 = 6j table builder, 1 = per-shell vertex assembly, 2 = shell-sum reduction,
+ * 3 = adjoint shell kernel, 4 = factorised (ring) vertex assembly.  eprl_timing_enable(ctx, 1) starts recording (clearing earlier
  * records), 0 stops.  eprl_timing_read synchronises the stream and returns the summed
  * duration in milliseconds and the number of launches recorded for `kernel`. */
 int eprl_timing_enable(eprl_ctx *ctx, int enable);

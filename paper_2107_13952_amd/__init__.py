@@ -39,8 +39,10 @@ _SIGS = {
     "eprl_destroy": (None, [ctypes.c_void_p]),
     "eprl_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "eprl_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "eprl_set_algorithm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "eprl_layout": (ctypes.c_int, [_i32p, ctypes.c_int, _i32p, _i32p, _i64p]),
     "eprl_count_terms": (ctypes.c_int, [_i32p, ctypes.c_int, _i64p, ctypes.POINTER(ctypes.c_double)]),
+    "eprl_count_work": (ctypes.c_int, [_i32p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "eprl_vertex_tensor": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_double, _dp, _dp]),
     "eprl_vertex_tensor_range": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_double, _dp,
                                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _dp]),
@@ -101,6 +103,15 @@ def count_terms(two_j, dl):
     if rc:
         raise EprlError(rc, "inadmissible spins or shell count")
     return live.value, terms.value
+
+
+def count_work(two_j, dl):
+    """dict: terms, shell_flops, ring_useful_flops, ring_mfma_flops (exact host counts)."""
+    out = (ctypes.c_double * 4)()
+    rc = _lib.eprl_count_work(_ints(two_j, 10), int(dl), out)
+    if rc:
+        raise EprlError(rc, "inadmissible spins or shell count")
+    return {"terms": out[0], "shell_flops": out[1], "ring_useful_flops": out[2], "ring_mfma_flops": out[3]}
 
 
 # ---------------------------------------------------------------- device calls
@@ -278,7 +289,14 @@ def shell_fifteenj(two_j, dl, shell, device="cuda"):
     return W[:n].reshape(shape)
 
 
-KERNELS = {"sixj_tables": 0, "assemble": 1, "reduce": 2, "adjoint_shells": 3}
+KERNELS = {"sixj_tables": 0, "assemble": 1, "reduce": 2, "adjoint_shells": 3, "ring": 4}
+ALGORITHMS = {"auto": 0, "shell": 1, "ring": 2}
+
+
+def set_algorithm(name, device="cuda"):
+    """Select how vertex tensors are evaluated: "auto" (default), "shell" or "ring"."""
+    ctx = _ctx(device)
+    ctx.check(_lib.eprl_set_algorithm(ctx.handle, ALGORITHMS[name]))
 
 
 def timing_enable(enable=True, device="cuda"):

@@ -27,6 +27,8 @@ struct eprl_ctx {
   int *primes = nullptr;
   int fact_max = -1;
   int nprime = 0;
+  // algorithm: EPRL_ALGO_AUTO, EPRL_ALGO_SHELL or EPRL_ALGO_RING
+  int algo = 0;
   // optional per-kernel timing
   bool timing = false;
   struct Rec {
@@ -176,7 +178,8 @@ struct Prepared {
 
 // Plan, size the workspace (tables + metadata + `extra` bytes), upload metadata and build the
 // 6j tables.  `extra` is placed at `prep.tail`.
-int prepare(eprl_ctx *c, const int two_j[10], int dl, size_t extra, Prepared &prep) {
+int prepare(eprl_ctx *c, const int two_j[10], int dl, size_t extra, Prepared &prep,
+            bool ring_tables = false) {
   int rc = make_plan(two_j, dl, prep.plan, c->err);
   if (rc) return rc;
   Plan &p = prep.plan;
@@ -218,7 +221,10 @@ int prepare(eprl_ctx *c, const int two_j[10], int dl, size_t extra, Prepared &pr
   tp.nprime = c->nprime;
   {
     TimedLaunch tl(c, 0);
-    HIP_TRY(c, launch_sixj_tables(tp, p.toff[5], c->stream));
+    if (ring_tables)
+      HIP_TRY(c, launch_ring_tables(tp, p.toff[5], c->stream));
+    else
+      HIP_TRY(c, launch_sixj_tables(tp, p.toff[5], c->stream));
   }
   return EPRL_OK;
 }
@@ -255,6 +261,72 @@ VertexParams vertex_params(const Prepared &prep, const double *B) {
 
 int check_ctx(eprl_ctx *c) { return c ? EPRL_OK : EPRL_EINVAL; }
 
+ReduceParams reduce_params(const Plan &p, const double *partial, int nchunk, double *A,
+                           int accumulate) {
+  ReduceParams rp;
+  rp.partial = partial;
+  rp.nchunk = nchunk;
+  rp.a_size = p.a_size;
+  for (int e = 0; e < 5; ++e) {
+    rp.i_lo2[e] = p.i[e].lo2;
+    rp.i_n[e] = p.i[e].n;
+  }
+  rp.A = A;
+  rp.accumulate = accumulate;
+  return rp;
+}
+
+// Factorised evaluation over all shells (one launch of the ring kernel, then the reduction).
+int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int accumulate,
+              double *A, const Plan &probe) {
+  const int64_t ncore = (int64_t)probe.nd * probe.nd * probe.nd * probe.nd;
+  int nchunk = (int)std::min<int64_t>(ncore, std::max(1, 2048 / probe.i[0].n));
+  const int64_t chunk = (ncore + nchunk - 1) / nchunk;
+  nchunk = (int)((ncore + chunk - 1) / chunk);
+  const size_t pbytes = align_up((size_t)nchunk * probe.a_size * sizeof(double), 256);
+  Prepared prep;
+  int rc = prepare(c, two_j, dl, pbytes, prep, true);
+  if (rc) return rc;
+  const Plan &p = prep.plan;
+  RingParams rp;
+  std::memset(&rp, 0, sizeof(rp));
+  std::memcpy(rp.two_j, p.two_j, sizeof(rp.two_j));
+  rp.nd = p.nd;
+  for (int e = 0; e < 5; ++e) {
+    rp.i_lo2[e] = p.i[e].lo2;
+    rp.i_n[e] = p.i[e].n;
+  }
+  for (int e = 0; e < 4; ++e) {
+    rp.K_lo2[e] = p.K[e].lo2;
+    rp.K_n[e] = p.K[e].n;
+  }
+  rp.X_lo2 = p.X.lo2;
+  rp.NX = p.X.n;
+  rp.U1 = prep.tables + p.toff[0];
+  rp.U2 = prep.tables + p.toff[1];
+  rp.U3 = prep.tables + p.toff[2];
+  rp.U4 = prep.tables + p.toff[3];
+  rp.U5 = prep.tables + p.toff[4];
+  rp.B = B;
+  rp.boff = prep.boff;
+  rp.kr = prep.kr;
+  rp.partial = reinterpret_cast<double *>(prep.tail);
+  rp.core_begin = 0;
+  rp.core_end = ncore;
+  rp.chunk = chunk;
+  rp.nchunk = nchunk;
+  {
+    TimedLaunch tl(c, 4);
+    HIP_TRY(c, launch_ring(rp, p.ring_KW, c->stream));
+  }
+  ReduceParams red = reduce_params(p, rp.partial, nchunk, A, accumulate);
+  {
+    TimedLaunch tl(c, 2);
+    HIP_TRY(c, launch_reduce(red, c->stream));
+  }
+  return EPRL_OK;
+}
+
 int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, const double *B,
                       int64_t sb, int64_t se, int accumulate, double *A) {
   if (!(gamma > 0.0) || !std::isfinite(gamma))
@@ -267,6 +339,13 @@ int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, co
     return fail(c, EPRL_EINVAL, "shell range outside [0, (dl+1)^6]");
   const int D = probe.D;
   if (D == 0) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
+  const bool full = sb == 0 && se == probe.nshell;
+  if (c->algo == EPRL_ALGO_RING && (!full || probe.ring_KW == 0))
+    return fail(c, EPRL_ERANGE,
+                "the factorised path needs the full shell range, i and k ranges <= 8 and core "
+                "windows <= 32");
+  if (full && c->algo != EPRL_ALGO_SHELL && probe.ring_KW != 0)
+    return ring_impl(c, two_j, dl, B, accumulate, A, probe);
   const int64_t nrange = std::max<int64_t>(se - sb, 1);
   const int target_wg = D == 8 ? 4096 : 1024;
   int nchunk = std::max(1, target_wg / probe.i[0].n);
@@ -339,6 +418,14 @@ void eprl_destroy(eprl_ctx *c) {
 
 const char *eprl_last_error(const eprl_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+int eprl_set_algorithm(eprl_ctx *c, int algo) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (algo != EPRL_ALGO_AUTO && algo != EPRL_ALGO_SHELL && algo != EPRL_ALGO_RING)
+    return fail(c, EPRL_EINVAL, "unknown algorithm");
+  c->algo = algo;
+  return EPRL_OK;
+}
+
 int eprl_set_stream(eprl_ctx *c, void *hip_stream) {
   if (check_ctx(c)) return EPRL_EINVAL;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -368,6 +455,16 @@ int eprl_count_terms(const int two_j[10], int dl, int64_t *live_shells, double *
   count_terms(p, live, t);
   if (live_shells) *live_shells = live;
   if (terms) *terms = t;
+  return EPRL_OK;
+}
+
+int eprl_count_work(const int two_j[10], int dl, double out[4]) {
+  if (!out) return EPRL_EINVAL;
+  Plan p;
+  std::string err;
+  int rc = make_plan(two_j, dl, p, err);
+  if (rc) return rc;
+  count_work(p, out);
   return EPRL_OK;
 }
 

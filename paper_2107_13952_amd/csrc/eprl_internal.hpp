@@ -38,12 +38,19 @@ struct Plan {
   int64_t tsize[5] = {0, 0, 0, 0, 0};
   int64_t toff[6] = {0, 0, 0, 0, 0, 0};
   int64_t a_size = 0;         // entries of the vertex tensor
+  // Factorised (ring) path: widest union over l45 of the k4 ranges of a core
+  // (l24, l34 fixed) and over l23 of the k3 ranges (l34, l35 fixed); the ring kernel needs
+  // them to fit its KW-wide LDS tiles, and all i and k ranges to fit 8.
+  int ring_w4 = 0, ring_w3 = 0;
+  int ring_KW = 0;            // 16 or 32 when the ring path applies, else 0
 };
 
 // Build a plan; returns EPRL_OK or an error code with a message in `err`.
 int make_plan(const int two_j[10], int dl, Plan &p, std::string &err);
 // Live-shell and term counts (host enumeration).
 void count_terms(const Plan &p, int64_t &live, double &terms);
+// Exact work counts: terms, per-shell-order flops, factorised-order useful and executed flops.
+void count_work(const Plan &p, double out[4]);
 // Primes up to n.
 std::vector<int> primes_upto(int n);
 
@@ -77,6 +84,21 @@ struct VertexParams {
   int nchunk;
 };
 
+struct RingParams {
+  int two_j[10];
+  int nd;
+  int i_lo2[5], i_n[5];
+  int K_lo2[4], K_n[4];
+  int X_lo2, NX;
+  const double *U1, *U2, *U3, *U4, *U5;
+  const double *B;
+  const int64_t *boff;
+  const int *kr;
+  double *partial;        // [nchunk][i1][i2][i3][i4][i5]
+  int64_t core_begin, core_end, chunk;
+  int nchunk;
+};
+
 struct ReduceParams {
   const double *partial;
   int nchunk;
@@ -90,10 +112,13 @@ struct ReduceParams {
 hipError_t launch_fexp_table(uint16_t *fexp, int fact_max, const int *primes, int nprime,
                              hipStream_t s);
 hipError_t launch_sixj_tables(const TableParams &tp, int64_t total, hipStream_t s);
+hipError_t launch_ring_tables(const TableParams &tp, int64_t total, hipStream_t s);
 hipError_t launch_sixj_batch(const int *args, int n, double *out, const uint16_t *fexp,
                              const int *primes, int nprime, int fact_max, hipStream_t s);
 hipError_t launch_assemble(const VertexParams &vp, int D, hipStream_t s);
 hipError_t launch_reduce(const ReduceParams &rp, hipStream_t s);
+size_t ring_smem_bytes(int KW, int nd);
+hipError_t launch_ring(const RingParams &rp, int KW, hipStream_t s);
 hipError_t launch_shell_fifteenj(const VertexParams &vp, int64_t shell, double *W,
                                  hipStream_t s);
 

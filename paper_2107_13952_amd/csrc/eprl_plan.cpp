@@ -170,6 +170,35 @@ int make_plan(const int two_j[10], int dl, Plan &p, std::string &err) {
   for (int t = 0; t < 5; ++t) p.toff[t + 1] = p.toff[t] + ((p.tsize[t] + 31) / 32) * 32;
   p.a_size = 1;
   for (int e = 0; e < 5; ++e) p.a_size *= p.i[e].n;
+  // Widest core windows of the factorised path.
+  p.ring_w4 = p.ring_w3 = 0;
+  for (int a = 0; a < nd; ++a) {
+    for (int b = 0; b < nd; ++b) {
+      int lo4 = 1 << 30, hi4 = -1, lo3 = 1 << 30, hi3 = -1;
+      for (int o = 0; o < nd; ++o) {
+        // edge 4 triple (l45, l24, l34) with (o24, o34) = (a, b)
+        const int t4 = (o * nd + a) * nd + b;
+        const int klo4 = p.kr[(2 * nd3 + t4) * 2], kn4 = p.kr[(2 * nd3 + t4) * 2 + 1];
+        if (kn4 > 0) {
+          lo4 = std::min(lo4, klo4);
+          hi4 = std::max(hi4, klo4 + 2 * (kn4 - 1));
+        }
+        // edge 3 triple (l34, l35, l23) with (o34, o35) = (a, b)
+        const int t3 = (a * nd + b) * nd + o;
+        const int klo3 = p.kr[(1 * nd3 + t3) * 2], kn3 = p.kr[(1 * nd3 + t3) * 2 + 1];
+        if (kn3 > 0) {
+          lo3 = std::min(lo3, klo3);
+          hi3 = std::max(hi3, klo3 + 2 * (kn3 - 1));
+        }
+      }
+      if (hi4 >= 0) p.ring_w4 = std::max(p.ring_w4, (hi4 - lo4) / 2 + 1);
+      if (hi3 >= 0) p.ring_w3 = std::max(p.ring_w3, (hi3 - lo3) / 2 + 1);
+    }
+  }
+  int ring_dmax = p.kmax;
+  for (int e = 0; e < 5; ++e) ring_dmax = std::max(ring_dmax, p.i[e].n);
+  const int w = std::max(p.ring_w4, p.ring_w3);
+  p.ring_KW = ring_dmax > 8 ? 0 : (w <= 16 ? 16 : (w <= 32 ? 32 : 0));
   return EPRL_OK;
 }
 
@@ -201,6 +230,124 @@ void count_terms(const Plan &p, int64_t &live, double &terms) {
     ++live;
     terms += prod;
   }
+}
+
+namespace {
+
+// Number of values v = lo, lo + 2, ... (n of them) with |a - v| <= x <= a + v, i.e. in the
+// triad (a, v, x).  All two-units.
+int triad_count(int lo, int n, int a, int x) {
+  if (n <= 0) return 0;
+  const int hi = lo + 2 * (n - 1);
+  const int vlo = std::max(lo, std::abs(x - a)), vhi = std::min(hi, x + a);
+  if (vlo > vhi) return 0;
+  if (((vlo - lo) & 1) != 0) return 0;  // parity mismatch: no value closes the triad
+  return (vhi - vlo) / 2 + 1;
+}
+
+}  // namespace
+
+void count_work(const Plan &p, double out[4]) {
+  const int nd = p.nd, nd3 = nd * nd * nd;
+  const int *J = p.two_j;
+  const int d1 = p.i[0].n, d2 = p.i[1].n, d3 = p.i[2].n, d4 = p.i[3].n, d5 = p.i[4].n;
+  const int xlo = p.X.lo2, xhi = p.X.lo2 + 2 * (p.X.n - 1);
+  double terms = 0, modes = 0, xterms = 0;
+  for (int64_t s = 0; s < p.nshell; ++s) {
+    int o[6];
+    int64_t r = s;
+    for (int q = 5; q >= 0; --q) {
+      o[q] = (int)(r % nd);
+      r /= nd;
+    }
+    const int t[4] = {(o[0] * nd + o[1]) * nd + o[2], (o[3] * nd + o[4]) * nd + o[0],
+                      (o[5] * nd + o[1]) * nd + o[3], (o[2] * nd + o[4]) * nd + o[5]};
+    int klo[4], kn[4];
+    bool live = true;
+    for (int e = 0; e < 4; ++e) {
+      klo[e] = p.kr[(e * nd3 + t[e]) * 2];
+      kn[e] = p.kr[(e * nd3 + t[e]) * 2 + 1];
+      live = live && kn[e] > 0;
+    }
+    if (!live) continue;
+    const double k2 = kn[0], k3 = kn[1], k4 = kn[2], k5 = kn[3];
+    terms += d1 * k2 * k3 * k4 * k5;
+    modes += d1 * k2 * k3 * k4 * k5 * d5 + d1 * k2 * k3 * k4 * d5 * d4 + d1 * k2 * k3 * d4 * d5 * d3 +
+             d1 * k2 * d3 * d4 * d5 * d2;
+    const int l24 = J[L24] + 2 * o[1], l25 = J[L25] + 2 * o[2], l35 = J[L35] + 2 * o[4];
+    for (int x = xlo; x <= xhi; x += 2) {
+      xterms += (double)triad_count(p.i[0].lo2, d1, l25, x) * triad_count(klo[3], kn[3], J[L14], x) *
+                triad_count(klo[2], kn[2], l35, x) * triad_count(klo[1], kn[1], l24, x) *
+                triad_count(klo[0], kn[0], J[L13], x);
+    }
+  }
+  out[0] = terms;
+  out[1] = 2.0 * modes + 6.0 * xterms;
+  // Factorised order: useful flops and MFMA-executed flops (padded tiles), as the ring
+  // kernel evaluates them: per (core, i1, x) with non-empty active k4 and k3 windows.
+  double useful = 0, executed = 0;
+  const int KW = p.ring_KW > 0 ? p.ring_KW : 16;
+  for (int o24 = 0; o24 < nd; ++o24)
+    for (int o25 = 0; o25 < nd; ++o25)
+      for (int o34 = 0; o34 < nd; ++o34)
+        for (int o35 = 0; o35 < nd; ++o35) {
+          const int l24 = J[L24] + 2 * o24, l25 = J[L25] + 2 * o25;
+          const int l34 = J[L34] + 2 * o34, l35 = J[L35] + 2 * o35;
+          (void)l34;
+          int lo5[64], n5[64], lo4[64], n4[64], lo2[64], n2[64], lo3[64], n3[64];
+          int w4lo = 1 << 30, w4hi = -1, w3lo = 1 << 30, w3hi = -1;
+          for (int o = 0; o < nd && o < 64; ++o) {
+            const int t5 = (o25 * nd + o35) * nd + o, t4 = (o * nd + o24) * nd + o34;
+            const int t2 = (o * nd + o24) * nd + o25, t3 = (o34 * nd + o35) * nd + o;
+            lo5[o] = p.kr[(3 * nd3 + t5) * 2];
+            n5[o] = p.kr[(3 * nd3 + t5) * 2 + 1];
+            lo4[o] = p.kr[(2 * nd3 + t4) * 2];
+            n4[o] = p.kr[(2 * nd3 + t4) * 2 + 1];
+            lo2[o] = p.kr[(0 * nd3 + t2) * 2];
+            n2[o] = p.kr[(0 * nd3 + t2) * 2 + 1];
+            lo3[o] = p.kr[(1 * nd3 + t3) * 2];
+            n3[o] = p.kr[(1 * nd3 + t3) * 2 + 1];
+            if (n5[o] == 0 || n4[o] == 0) n5[o] = n4[o] = 0;
+            if (n2[o] == 0 || n3[o] == 0) n2[o] = n3[o] = 0;
+            if (n4[o] > 0) {
+              w4lo = std::min(w4lo, lo4[o]);
+              w4hi = std::max(w4hi, lo4[o] + 2 * (n4[o] - 1));
+            }
+            if (n3[o] > 0) {
+              w3lo = std::min(w3lo, lo3[o]);
+              w3hi = std::max(w3hi, lo3[o] + 2 * (n3[o] - 1));
+            }
+          }
+          if (w4hi < 0 || w3hi < 0) continue;
+          for (int n1 = 0; n1 < d1; ++n1) {
+            const int i1 = p.i[0].lo2 + 2 * n1;
+            const int xa = std::max(std::abs(i1 - l25), xlo), xb = std::min(i1 + l25, xhi);
+            for (int x = xa; x <= xb; x += 2) {
+              const int a4 = std::max(w4lo, std::abs(l35 - x)), b4 = std::min(w4hi, l35 + x);
+              const int a3 = std::max(w3lo, std::abs(l24 - x)), b3 = std::min(w3hi, l24 + x);
+              if (a4 > b4 || a3 > b3) continue;
+              const int na4 = (b4 - a4) / 2 + 1, na3 = (b3 - a3) / 2 + 1;
+              for (int o = 0; o < nd && o < 64; ++o) {
+                if (n5[o] > 0) {
+                  const int c4 = triad_count(lo4[o], n4[o], l35, x);
+                  const int c5 = triad_count(lo5[o], n5[o], J[L14], x);
+                  useful += (double)d5 * c4 * (3.0 * c5 + 2.0 * d4);
+                }
+                if (n2[o] > 0) {
+                  const int c3 = triad_count(lo3[o], n3[o], l24, x);
+                  const int c2 = triad_count(lo2[o], n2[o], J[L13], x);
+                  useful += (double)d2 * c3 * (3.0 * c2 + 2.0 * d3);
+                }
+              }
+              useful += 2.0 * d5 * d4 * na4 * na3 + 2.0 * d5 * d4 * na3 * d3 * d2;
+              const int s4 = ((b4 - w4lo) / 2) / 4 - ((a4 - w4lo) / 2) / 4 + 1;
+              const int s3 = ((b3 - w3lo) / 2) / 4 - ((a3 - w3lo) / 2) / 4 + 1;
+              executed += 2.0 * 64 * KW * 4 * s4 + 2.0 * 64 * 64 * 4 * s3;
+            }
+          }
+        }
+  out[2] = useful;
+  out[3] = executed;
 }
 
 }  // namespace eprl

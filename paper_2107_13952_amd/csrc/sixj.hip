@@ -244,6 +244,81 @@ __global__ void sixj_table_kernel(TableParams tp, int64_t total) {
                              tp.primes, tp.nprime);
 }
 
+// Signed, x-major tables for the factorised (ring) assembly.  The phase (-1)^R of eq. (15j)
+// splits over the five closed triads (i1 j12 j13), (k2 l23 l24), (k3 l34 l35), (k4 j14 l45),
+// (k5 j15 l25), each with an integer half-sum r_n; every factor goes into the one table that
+// carries all of its spins, and (2x+1) goes into the first table:
+//   U1[o25][x][i1][k5]  = (2x+1) (-1)^{r1 + r5} {i1 l25 x; k5 j14 j15}
+//   U2[o35][o45][x][k5][k4] = (-1)^{r4} {j14 k5 x; l35 k4 l45}
+//   U3[o24][o34][o35][x][k4][k3] = (-1)^{r3} {k4 l35 x; k3 l24 l34}
+//   U4[o23][o24][x][k3][k2] = (-1)^{r2} {l24 k3 x; j13 k2 l23}
+//   U5[o25][x][k2][i1]  = {k2 j13 x; i1 l25 j12}
+// so that W(i1, k2..k5) = sum_x U1 U2 U3 U4 U5 exactly.
+__global__ void ring_table_kernel(TableParams tp, int64_t total) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  int t = 0;
+  while (t < 4 && g >= tp.toff[t + 1]) ++t;
+  int64_t idx = g - tp.toff[t];
+  const int nd = tp.nd;
+  const int *J = tp.two_j;
+  const int NX = tp.NX;
+  const int n1 = tp.i1_n, nK2 = tp.K_n[0], nK3 = tp.K_n[1], nK4 = tp.K_n[2], nK5 = tp.K_n[3];
+  int64_t size;
+  switch (t) {
+    case 0: size = (int64_t)nd * NX * n1 * nK5; break;
+    case 1: size = (int64_t)nd * nd * NX * nK5 * nK4; break;
+    case 2: size = (int64_t)nd * nd * nd * NX * nK4 * nK3; break;
+    case 3: size = (int64_t)nd * nd * NX * nK3 * nK2; break;
+    default: size = (int64_t)nd * NX * nK2 * n1; break;
+  }
+  if (idx >= size) return;
+  int64_t r = idx;
+  double v = 0.0;
+  int ph = 0;  // exponent of -1 (two-units, halved below)
+  if (t == 0) {
+    const int k5 = tp.K_lo2[3] + 2 * (int)(r % nK5); r /= nK5;
+    const int i1 = tp.i1_lo2 + 2 * (int)(r % n1); r /= n1;
+    const int x = tp.X_lo2 + 2 * (int)(r % NX); r /= NX;
+    const int l25 = J[L25] + 2 * (int)r;
+    v = (double)(x + 1) * sixj_device(i1, l25, x, k5, J[L14], J[L15], tp.fexp, tp.primes, tp.nprime);
+    ph = (i1 + J[L12] + J[L13]) / 2 + (k5 + J[L15] + l25) / 2;
+  } else if (t == 1) {
+    const int k4 = tp.K_lo2[2] + 2 * (int)(r % nK4); r /= nK4;
+    const int k5 = tp.K_lo2[3] + 2 * (int)(r % nK5); r /= nK5;
+    const int x = tp.X_lo2 + 2 * (int)(r % NX); r /= NX;
+    const int l45 = J[L45] + 2 * (int)(r % nd); r /= nd;
+    const int l35 = J[L35] + 2 * (int)r;
+    v = sixj_device(J[L14], k5, x, l35, k4, l45, tp.fexp, tp.primes, tp.nprime);
+    ph = (k4 + J[L14] + l45) / 2;
+  } else if (t == 2) {
+    const int k3 = tp.K_lo2[1] + 2 * (int)(r % nK3); r /= nK3;
+    const int k4 = tp.K_lo2[2] + 2 * (int)(r % nK4); r /= nK4;
+    const int x = tp.X_lo2 + 2 * (int)(r % NX); r /= NX;
+    const int l35 = J[L35] + 2 * (int)(r % nd); r /= nd;
+    const int l34 = J[L34] + 2 * (int)(r % nd); r /= nd;
+    const int l24 = J[L24] + 2 * (int)r;
+    v = sixj_device(k4, l35, x, k3, l24, l34, tp.fexp, tp.primes, tp.nprime);
+    ph = (k3 + l34 + l35) / 2;
+  } else if (t == 3) {
+    const int k2 = tp.K_lo2[0] + 2 * (int)(r % nK2); r /= nK2;
+    const int k3 = tp.K_lo2[1] + 2 * (int)(r % nK3); r /= nK3;
+    const int x = tp.X_lo2 + 2 * (int)(r % NX); r /= NX;
+    const int l24 = J[L24] + 2 * (int)(r % nd); r /= nd;
+    const int l23 = J[L23] + 2 * (int)r;
+    v = sixj_device(l24, k3, x, J[L13], k2, l23, tp.fexp, tp.primes, tp.nprime);
+    ph = (k2 + l23 + l24) / 2;
+  } else {
+    const int i1 = tp.i1_lo2 + 2 * (int)(r % n1); r /= n1;
+    const int k2 = tp.K_lo2[0] + 2 * (int)(r % nK2); r /= nK2;
+    const int x = tp.X_lo2 + 2 * (int)(r % NX); r /= NX;
+    const int l25 = J[L25] + 2 * (int)r;
+    v = sixj_device(k2, J[L13], x, i1, l25, J[L12], tp.fexp, tp.primes, tp.nprime);
+    ph = 0;
+  }
+  tp.tables[g] = (ph & 1) ? -v : v;
+}
+
 __global__ void sixj_batch_kernel(const int *args, int n, double *out, const uint16_t *fexp,
                                   const int *primes, int nprime, int fact_max) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -271,6 +346,12 @@ hipError_t launch_fexp_table(uint16_t *fexp, int fact_max, const int *primes, in
 hipError_t launch_sixj_tables(const TableParams &tp, int64_t total, hipStream_t s) {
   int64_t blocks = (total + 255) / 256;
   sixj_table_kernel<<<(unsigned)blocks, 256, 0, s>>>(tp, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_ring_tables(const TableParams &tp, int64_t total, hipStream_t s) {
+  int64_t blocks = (total + 255) / 256;
+  ring_table_kernel<<<(unsigned)blocks, 256, 0, s>>>(tp, total);
   return hipGetLastError();
 }
 
