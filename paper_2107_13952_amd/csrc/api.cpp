@@ -36,6 +36,16 @@ struct eprl_ctx {
     hipEvent_t start, stop;
   };
   std::vector<Rec> recs;
+  bool capturing = false;
+  // Batched path: a dedicated workspace and the instantiated graph of the last batch.
+  struct Batch {
+    std::vector<int64_t> key;
+    char *ws = nullptr;
+    size_t ws_size = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;  // private stream the graph is captured on (default priority)
+  } batch;
 };
 
 namespace {
@@ -63,7 +73,7 @@ struct TimedLaunch {
   int kernel;
   hipEvent_t start = nullptr, stop = nullptr;
   TimedLaunch(eprl_ctx *c_, int k) : c(c_), kernel(k) {
-    if (!c->timing) return;
+    if (!c->timing || c->capturing) return;
     if (hipEventCreate(&start) != hipSuccess || hipEventCreate(&stop) != hipSuccess) {
       (void)hipGetLastError();
       start = stop = nullptr;
@@ -382,6 +392,292 @@ int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, co
   return EPRL_OK;
 }
 
+
+// ---- batched path ------------------------------------------------------------------------
+//
+// All configurations of a batch share one dedicated workspace laid out once per batch shape:
+// for each configuration its 6j tables, booster offsets and k ranges, and its per-chunk partial
+// sums; then the RingParams array and the work list of the persistent ring kernel.  The
+// device work (table builds, one persistent ring launch for every configuration the
+// factorised path handles, per-shell launches for the others, reductions) is captured once
+// into a hipGraph and replayed while the batch (spins, shell counts, pointers, algorithm)
+// stays the same.  Chunking per configuration equals the single-configuration path, so every
+// tensor is bitwise identical to a separate eprl_vertex_tensor call.
+
+struct BatchEntry {
+  Plan plan;
+  bool ring = false;
+  size_t tables = 0, boff = 0, kr = 0, partial = 0;  // byte offsets in the batch workspace
+  int nchunk = 0;
+  int64_t chunk = 0;
+};
+
+int batch_chunks(const Plan &p, bool ring, int &nchunk, int64_t &chunk) {
+  if (ring) {
+    const int64_t ncore = (int64_t)p.nd * p.nd * p.nd * p.nd;
+    nchunk = (int)std::min<int64_t>(ncore, std::max(1, 2048 / p.i[0].n));
+    chunk = (ncore + nchunk - 1) / nchunk;
+    nchunk = (int)((ncore + chunk - 1) / chunk);
+  } else {
+    const int target_wg = p.D == 8 ? 4096 : 1024;
+    nchunk = std::max(1, target_wg / p.i[0].n);
+    chunk = (p.nshell + nchunk - 1) / nchunk;
+    nchunk = (int)((p.nshell + chunk - 1) / chunk);
+  }
+  return EPRL_OK;
+}
+
+TableParams table_params(const Plan &p, double *tables, const eprl_ctx *c) {
+  TableParams tp;
+  std::memcpy(tp.two_j, p.two_j, sizeof(tp.two_j));
+  tp.nd = p.nd;
+  tp.i1_lo2 = p.i[0].lo2;
+  tp.i1_n = p.i[0].n;
+  for (int e = 0; e < 4; ++e) {
+    tp.K_lo2[e] = p.K[e].lo2;
+    tp.K_n[e] = p.K[e].n;
+  }
+  tp.X_lo2 = p.X.lo2;
+  tp.NX = p.X.n;
+  for (int t = 0; t < 6; ++t) tp.toff[t] = p.toff[t];
+  tp.tables = tables;
+  tp.fexp = c->fexp;
+  tp.primes = c->primes;
+  tp.nprime = c->nprime;
+  return tp;
+}
+
+int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
+                 const double *const *boosters, double *const *A) {
+  std::vector<int64_t> key;
+  key.push_back(n);
+  key.push_back(c->algo);
+  for (int q = 0; q < n; ++q) {
+    for (int t = 0; t < 10; ++t) key.push_back(two_j[10 * q + t]);
+    key.push_back(dl[q]);
+    key.push_back((int64_t)(uintptr_t)boosters[q]);
+    key.push_back((int64_t)(uintptr_t)A[q]);
+    if (!boosters[q] || !A[q]) return fail(c, EPRL_EINVAL, "null booster or output pointer");
+  }
+  if (c->batch.exec && key == c->batch.key) {
+    HIP_TRY(c, hipGraphLaunch(c->batch.exec, c->stream));
+    return EPRL_OK;
+  }
+  // New batch shape: plan every configuration and lay out the workspace.
+  std::vector<BatchEntry> ent(n);
+  size_t off = 0;
+  int fact_max = 0, KW = 0, max_nd = 1;
+  for (int q = 0; q < n; ++q) {
+    BatchEntry &b = ent[q];
+    std::string err;
+    int rc = make_plan(two_j + 10 * q, dl[q], b.plan, err);
+    if (rc) {
+      std::ostringstream os;
+      os << "configuration " << q << ": " << err;
+      return fail(c, rc, os.str());
+    }
+    const Plan &p = b.plan;
+    if (p.D == 0) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
+    b.ring = c->algo != EPRL_ALGO_SHELL && p.ring_KW != 0;
+    if (c->algo == EPRL_ALGO_RING && !b.ring)
+      return fail(c, EPRL_ERANGE, "the factorised path does not apply to every configuration");
+    batch_chunks(p, b.ring, b.nchunk, b.chunk);
+    fact_max = std::max(fact_max, p.fact_max);
+    if (b.ring) {
+      KW = std::max(KW, p.ring_KW);
+      max_nd = std::max(max_nd, p.nd);
+    }
+    b.tables = off;
+    off += align_up((size_t)p.toff[5] * sizeof(double), 256);
+    b.boff = off;
+    off += align_up(p.boff.size() * sizeof(int64_t), 256);
+    b.kr = off;
+    off += align_up(p.kr.size() * sizeof(int), 256);
+    b.partial = off;
+    off += align_up((size_t)b.nchunk * p.a_size * sizeof(double), 256);
+  }
+  // Work list of the persistent kernel: (configuration, chunk, i1), longest first.
+  struct Item {
+    double cost;
+    int cfg, chunk, n1;
+  };
+  std::vector<Item> items;
+  std::vector<int> ring_index(n, -1);
+  int nring = 0;
+  for (int q = 0; q < n; ++q) {
+    if (!ent[q].ring) continue;
+    ring_index[q] = nring++;
+    double w[4];
+    count_work(ent[q].plan, w);
+    const double per = w[3] / ((double)ent[q].nchunk * ent[q].plan.i[0].n);
+    for (int ch = 0; ch < ent[q].nchunk; ++ch)
+      for (int n1 = 0; n1 < ent[q].plan.i[0].n; ++n1) items.push_back({per, ring_index[q], ch, n1});
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const Item &a, const Item &b) { return a.cost > b.cost; });
+  const size_t params_off = off;
+  off += align_up((size_t)std::max(nring, 1) * sizeof(RingParams), 256);
+  const size_t items_off = off;
+  off += align_up(std::max<size_t>(items.size(), 1) * 3 * sizeof(int), 256);
+  int rc = ensure_fexp(c, fact_max);
+  if (rc) return rc;
+  // Drop the previous graph and workspace.
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->batch.exec) (void)hipGraphExecDestroy(c->batch.exec);
+  if (c->batch.graph) (void)hipGraphDestroy(c->batch.graph);
+  c->batch.exec = nullptr;
+  c->batch.graph = nullptr;
+  c->batch.key.clear();
+  if (off > c->batch.ws_size) {
+    if (c->batch.ws) (void)hipFree(c->batch.ws);
+    c->batch.ws = nullptr;
+    c->batch.ws_size = 0;
+    if (hipMalloc(&c->batch.ws, off) != hipSuccess) {
+      (void)hipGetLastError();
+      c->batch.ws = nullptr;
+      return fail(c, EPRL_ENOMEM, "batch workspace allocation failed");
+    }
+    c->batch.ws_size = off;
+  }
+  char *ws = c->batch.ws;
+  // Metadata upload (outside the graph; the workspace belongs to this batch only).
+  std::vector<RingParams> params(std::max(nring, 1));
+  for (int q = 0; q < n; ++q) {
+    if (!ent[q].ring) continue;
+    const Plan &p = ent[q].plan;
+    RingParams &rp = params[ring_index[q]];
+    std::memset(&rp, 0, sizeof(rp));
+    std::memcpy(rp.two_j, p.two_j, sizeof(rp.two_j));
+    rp.nd = p.nd;
+    for (int e = 0; e < 5; ++e) {
+      rp.i_lo2[e] = p.i[e].lo2;
+      rp.i_n[e] = p.i[e].n;
+    }
+    for (int e = 0; e < 4; ++e) {
+      rp.K_lo2[e] = p.K[e].lo2;
+      rp.K_n[e] = p.K[e].n;
+    }
+    rp.X_lo2 = p.X.lo2;
+    rp.NX = p.X.n;
+    const double *tab = reinterpret_cast<const double *>(ws + ent[q].tables);
+    rp.U1 = tab + p.toff[0];
+    rp.U2 = tab + p.toff[1];
+    rp.U3 = tab + p.toff[2];
+    rp.U4 = tab + p.toff[3];
+    rp.U5 = tab + p.toff[4];
+    rp.B = boosters[q];
+    rp.boff = reinterpret_cast<const int64_t *>(ws + ent[q].boff);
+    rp.kr = reinterpret_cast<const int *>(ws + ent[q].kr);
+    rp.partial = reinterpret_cast<double *>(ws + ent[q].partial);
+    rp.core_begin = 0;
+    rp.core_end = (int64_t)p.nd * p.nd * p.nd * p.nd;
+    rp.chunk = ent[q].chunk;
+    rp.nchunk = ent[q].nchunk;
+  }
+  // Compact staging of the metadata blocks: (workspace offset, bytes) in staging order.
+  std::vector<std::pair<size_t, size_t>> blocks;
+  size_t sbytes = 0;
+  for (int q = 0; q < n; ++q) {
+    blocks.push_back({ent[q].boff, ent[q].partial - ent[q].boff});  // boff and kr
+    sbytes += ent[q].partial - ent[q].boff;
+  }
+  blocks.push_back({params_off, off - params_off});                  // params and items
+  sbytes += off - params_off;
+  char *st;
+  rc = staging(c, sbytes, &st);
+  if (rc) return rc;
+  {
+    size_t so = 0;
+    for (int q = 0; q < n; ++q) {
+      const Plan &p = ent[q].plan;
+      std::memcpy(st + so, p.boff.data(), p.boff.size() * sizeof(int64_t));
+      std::memcpy(st + so + (ent[q].kr - ent[q].boff), p.kr.data(), p.kr.size() * sizeof(int));
+      so += ent[q].partial - ent[q].boff;
+    }
+    std::memcpy(st + so, params.data(), params.size() * sizeof(RingParams));
+    std::vector<int> flat(std::max<size_t>(items.size(), 1) * 3, 0);
+    for (size_t k = 0; k < items.size(); ++k) {
+      flat[3 * k] = items[k].cfg;
+      flat[3 * k + 1] = items[k].chunk;
+      flat[3 * k + 2] = items[k].n1;
+    }
+    std::memcpy(st + so + (items_off - params_off), flat.data(), flat.size() * sizeof(int));
+    so = 0;
+    for (auto &b : blocks) {
+      HIP_TRY(c, hipMemcpyAsync(ws + b.first, st + so, b.second, hipMemcpyHostToDevice, c->stream));
+      so += b.second;
+    }
+  }
+  HIP_TRY(c, hipEventRecord(c->stage_done, c->stream));
+  c->stage_pending = true;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  // Capture the device work on a private stream (the caller's stream may be the null stream,
+  // which cannot be captured); the graph is then launched on the caller's stream.
+  if (!c->batch.cap) HIP_TRY(c, hipStreamCreateWithFlags(&c->batch.cap, hipStreamNonBlocking));
+  hipStream_t user = c->stream;
+  c->stream = c->batch.cap;
+  hipError_t eb = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) {
+    c->stream = user;
+    return hip_fail(c, eb, "hipStreamBeginCapture");
+  }
+  c->capturing = true;
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < n && e == hipSuccess; ++q) {
+    TableParams tp = table_params(ent[q].plan, reinterpret_cast<double *>(ws + ent[q].tables), c);
+    e = ent[q].ring ? launch_ring_tables(tp, ent[q].plan.toff[5], c->stream)
+                    : launch_sixj_tables(tp, ent[q].plan.toff[5], c->stream);
+  }
+  if (e == hipSuccess && nring > 0) {
+    const int grid = (int)std::min<size_t>(items.size(), (size_t)ncu * 4);
+    e = launch_ring_batch(reinterpret_cast<const RingParams *>(ws + params_off),
+                          reinterpret_cast<const int *>(ws + items_off), (int)items.size(), KW,
+                          max_nd, grid, c->stream);
+  }
+  for (int q = 0; q < n && e == hipSuccess; ++q) {
+    if (ent[q].ring) continue;
+    Prepared prep;
+    prep.plan = ent[q].plan;
+    prep.tables = reinterpret_cast<double *>(ws + ent[q].tables);
+    prep.boff = reinterpret_cast<int64_t *>(ws + ent[q].boff);
+    prep.kr = reinterpret_cast<int *>(ws + ent[q].kr);
+    VertexParams vp = vertex_params(prep, boosters[q]);
+    vp.partial = reinterpret_cast<double *>(ws + ent[q].partial);
+    vp.shell_begin = 0;
+    vp.shell_end = ent[q].plan.nshell;
+    vp.chunk = ent[q].chunk;
+    vp.nchunk = ent[q].nchunk;
+    e = launch_assemble(vp, ent[q].plan.D, c->stream);
+  }
+  for (int q = 0; q < n && e == hipSuccess; ++q) {
+    ReduceParams red = reduce_params(ent[q].plan, reinterpret_cast<double *>(ws + ent[q].partial),
+                                     ent[q].nchunk, A[q], 0);
+    e = launch_reduce(red, c->stream);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+  c->capturing = false;
+  c->stream = user;
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(c, e, "batched launch sequence");
+  }
+  if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(c, e, "hipGraphInstantiate");
+  }
+  c->batch.graph = graph;
+  c->batch.exec = exec;
+  c->batch.key = key;
+  HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+  return EPRL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -393,7 +689,8 @@ int eprl_create(eprl_ctx **out, int device, void *hip_stream) {
   if (!c) return EPRL_ENOMEM;
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  if (hipSetDevice(device) != hipSuccess || hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
+  if (hipSetDevice(device) != hipSuccess || ring_init_attributes() != hipSuccess ||
+      hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     delete c;
     return EPRL_EHIP;
@@ -412,6 +709,10 @@ void eprl_destroy(eprl_ctx *c) {
   if (c->fexp) (void)hipFree(c->fexp);
   if (c->primes) (void)hipFree(c->primes);
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  if (c->batch.exec) (void)hipGraphExecDestroy(c->batch.exec);
+  if (c->batch.graph) (void)hipGraphDestroy(c->batch.graph);
+  if (c->batch.ws) (void)hipFree(c->batch.ws);
+  if (c->batch.cap) (void)hipStreamDestroy(c->batch.cap);
   clear_timing(c);
   delete c;
 }
@@ -489,11 +790,10 @@ int eprl_vertex_tensor_batched(eprl_ctx *c, int n, const int *two_j, const int *
   if (check_ctx(c)) return EPRL_EINVAL;
   if (n < 0 || (n > 0 && (!two_j || !dl || !boosters || !A)))
     return fail(c, EPRL_EINVAL, "invalid batch arguments");
-  for (int q = 0; q < n; ++q) {
-    int rc = eprl_vertex_tensor(c, two_j + 10 * q, dl[q], gamma, boosters[q], A[q]);
-    if (rc) return rc;
-  }
-  return EPRL_OK;
+  if (!(gamma > 0.0) || !std::isfinite(gamma))
+    return fail(c, EPRL_EINVAL, "gamma must be finite and positive");
+  if (n == 0) return EPRL_OK;
+  return batched_impl(c, n, two_j, dl, boosters, A);
 }
 
 int eprl_contract_boundary(eprl_ctx *c, const int dims_i[5], const double *A,

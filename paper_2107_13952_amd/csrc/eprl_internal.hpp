@@ -118,7 +118,12 @@ hipError_t launch_sixj_batch(const int *args, int n, double *out, const uint16_t
 hipError_t launch_assemble(const VertexParams &vp, int D, hipStream_t s);
 hipError_t launch_reduce(const ReduceParams &rp, hipStream_t s);
 size_t ring_smem_bytes(int KW, int nd);
+// Largest dl + 1 the ring kernels stage booster blocks for.
+constexpr int kRingMaxNd = 16;
+hipError_t ring_init_attributes();
 hipError_t launch_ring(const RingParams &rp, int KW, hipStream_t s);
+hipError_t launch_ring_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems, int KW,
+                             int max_nd, int grid, hipStream_t s);
 hipError_t launch_shell_fifteenj(const VertexParams &vp, int64_t shell, double *W,
                                  hipStream_t s);
 

@@ -198,7 +198,7 @@ int make_plan(const int two_j[10], int dl, Plan &p, std::string &err) {
   int ring_dmax = p.kmax;
   for (int e = 0; e < 5; ++e) ring_dmax = std::max(ring_dmax, p.i[e].n);
   const int w = std::max(p.ring_w4, p.ring_w3);
-  p.ring_KW = ring_dmax > 8 ? 0 : (w <= 16 ? 16 : (w <= 32 ? 32 : 0));
+  p.ring_KW = (ring_dmax > 8 || nd > kRingMaxNd) ? 0 : (w <= 16 ? 16 : (w <= 32 ? 32 : 0));
   return EPRL_OK;
 }
 

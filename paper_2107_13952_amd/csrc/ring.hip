@@ -34,9 +34,9 @@ __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
+// One work item: cores [chunk * rp.chunk, ...) of rp, boundary intertwiner i1 = n1.
 template <int KW>
-__global__ __launch_bounds__(RT) void ring_kernel(RingParams rp) {
-  extern __shared__ double smem[];
+__device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, double *smem) {
   constexpr int GS = KW + 1;  // padded row stride of G and P
   const int nd = rp.nd, nd3 = nd * nd * nd;
   double *Gs = smem;                  // [64][GS]  rows (i5, i4), cols k4
@@ -47,7 +47,6 @@ __global__ __launch_bounds__(RT) void ring_kernel(RingParams rp) {
   int *rng = reinterpret_cast<int *>(Mb + 4 * nd * 64);  // [8][nd]: lo/n of k5, k4, k2, k3
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n1 = blockIdx.y;
   const int *J = rp.two_j;
   const int two_i1 = rp.i_lo2[0] + 2 * n1;
   const int d1 = rp.i_n[0], d2 = rp.i_n[1], d3 = rp.i_n[2], d4 = rp.i_n[3], d5 = rp.i_n[4];
@@ -58,7 +57,7 @@ __global__ __launch_bounds__(RT) void ring_kernel(RingParams rp) {
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) acc[cb] = d4v{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t c0 = rp.core_begin + (int64_t)blockIdx.x * rp.chunk;
+  const int64_t c0 = rp.core_begin + chunk_index * rp.chunk;
   const int64_t c1 = c0 + rp.chunk < rp.core_end ? c0 + rp.chunk : rp.core_end;
   for (int64_t core = c0; core < c1; ++core) {
     const int o24 = (int)(core / (nd * nd * nd)), o25 = (int)((core / (nd * nd)) % nd);
@@ -230,7 +229,7 @@ __global__ __launch_bounds__(RT) void ring_kernel(RingParams rp) {
   }
   // Flush the chunk's partial A(i1, ...): row (i5, i4), column (i3, i2).
   const int64_t slice = (int64_t)d2 * d3 * d4 * d5;
-  double *out = rp.partial + ((int64_t)blockIdx.x * d1 + n1) * slice;
+  double *out = rp.partial + (chunk_index * d1 + n1) * slice;
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
@@ -240,6 +239,26 @@ __global__ __launch_bounds__(RT) void ring_kernel(RingParams rp) {
       if (i2 < d2 && i3 < d3 && i4 < d4 && i5 < d5)
         out[((i2 * d3 + i3) * d4 + i4) * d5 + i5] = acc[cb][j];
     }
+  }
+  __syncthreads();  // the next item reuses the LDS
+}
+
+template <int KW>
+__global__ __launch_bounds__(RT) void ring_kernel(RingParams rp) {
+  extern __shared__ double smem[];
+  ring_item<KW>(rp, blockIdx.x, blockIdx.y, smem);
+}
+
+// Persistent variant for batches: every workgroup walks a static, longest-first list of
+// (configuration, chunk, i1) items with stride gridDim.x; no atomics, so the assignment of
+// items to workgroups (and every partial sum) is fixed.
+template <int KW>
+__global__ __launch_bounds__(RT) void ring_batch_kernel(const RingParams *cfgs, const int *items,
+                                                        int nitems) {
+  extern __shared__ double smem[];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int c = items[3 * it], chunk = items[3 * it + 1], n1 = items[3 * it + 2];
+    ring_item<KW>(cfgs[c], chunk, n1, smem);
   }
 }
 
@@ -251,19 +270,40 @@ size_t ring_smem_bytes(int KW, int nd) {
          sizeof(int) * (size_t)(8 * nd);
 }
 
+// Allow the ring kernels the dynamic LDS of the largest supported configuration.  Called once
+// per process before any launch (not a stream operation, so never inside a graph capture).
+hipError_t ring_init_attributes() {
+  const int bytes = (int)ring_smem_bytes(32, kRingMaxNd);
+  const void *fns[4] = {(const void *)ring_kernel<16>, (const void *)ring_kernel<32>,
+                        (const void *)ring_batch_kernel<16>, (const void *)ring_batch_kernel<32>};
+  for (const void *f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_ring(const RingParams &rp, int KW, hipStream_t s) {
   dim3 grid(rp.nchunk, rp.i_n[0], 1);
   const size_t shm = ring_smem_bytes(KW, rp.nd);
   if (KW == 16) {
-    hipError_t e = hipFuncSetAttribute((const void *)ring_kernel<16>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
     ring_kernel<16><<<grid, RT, shm, s>>>(rp);
   } else if (KW == 32) {
-    hipError_t e = hipFuncSetAttribute((const void *)ring_kernel<32>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
     ring_kernel<32><<<grid, RT, shm, s>>>(rp);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ring_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems, int KW,
+                             int max_nd, int grid, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  const size_t shm = ring_smem_bytes(KW, max_nd);
+  if (KW == 16) {
+    ring_batch_kernel<16><<<grid, RT, shm, s>>>(cfgs_dev, items_dev, nitems);
+  } else if (KW == 32) {
+    ring_batch_kernel<32><<<grid, RT, shm, s>>>(cfgs_dev, items_dev, nitems);
   } else {
     return hipErrorInvalidValue;
   }
