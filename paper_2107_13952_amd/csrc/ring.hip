@@ -44,7 +44,11 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, dou
   double *Hs = Ps + 64 * GS;          // [KW][64]  rows k3, cols (i3, i2)
   double *U3s = Hs + KW * 64;         // [KW][KW]  k4 x k3
   double *Mb = U3s + KW * KW;         // [4][nd][8][8]: M5, M4 (per o45), M2, M3 (per o23)
-  int *rng = reinterpret_cast<int *>(Mb + 4 * nd * 64);  // [8][nd]: lo/n of k5, k4, k2, k3
+  double *U2s = Mb + 4 * nd * 64;     // [nd][8][KW]  per o45: active k5 x core-window k4
+  double *U4s = U2s + nd * 8 * KW;    // [nd][KW][8]  per o23: core-window k3 x active k2
+  double *U1s = U4s + nd * KW * 8;    // [nd][8]      per o45: active k5
+  double *U5s = U1s + nd * 8;         // [nd][8]      per o23: active k2
+  int *rng = reinterpret_cast<int *>(U5s + nd * 8);  // [8][nd]: lo/n of k5, k4, k2, k3
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int *J = rp.two_j;
@@ -124,16 +128,61 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, dou
       const int a4l = (a4 - w4lo) / 2, b4l = (b4 - w4lo) / 2;
       const int a3l = (a3 - w3lo) / 2, b3l = (b3 - w3lo) / 2;
       __syncthreads();  // previous x's readers of Gs / Hs / U3s / Ps are done
-      // U3 slice of this x, zero outside the active windows.
-      for (int idx = tid; idx < KW * KW; idx += RT) {
-        const int k4l = idx / KW, k3l = idx % KW;
-        double v = 0.0;
-        if (k4l >= a4l && k4l <= b4l && k3l >= a3l && k3l <= b3l) {
-          const int k4g = (w4lo - rp.K_lo2[2]) / 2 + k4l, k3g = (w3lo - rp.K_lo2[1]) / 2 + k3l;
-          v = rp.U3[((u3base + xg) * nK4 + k4g) * nK3 + k3g];
+      // Stage every 6j slice this x needs, zero outside the active windows:
+      // U3 (k4 x k3); per l45 the active k5 of its range (at most 8) with U1 and U2 (k5 x k4
+      // window); per l23 the active k2 of its range with U5 and U4 (k3 window x k2).
+      const int x14lo = iabs(x - J[L14]), x14hi = x + J[L14];
+      const int x13lo = iabs(J[L13] - x), x13hi = J[L13] + x;
+      const int k4g0 = (w4lo - rp.K_lo2[2]) / 2, k3g0 = (w3lo - rp.K_lo2[1]) / 2;
+      {
+        const int n_u3 = KW * KW, n_u2 = nd * 8 * KW, n_u4 = nd * KW * 8, n_v = 2 * nd * 8;
+        const int total = n_u3 + n_u2 + n_u4 + n_v;
+        for (int idx = tid; idx < total; idx += RT) {
+          double v = 0.0;
+          if (idx < n_u3) {
+            const int k4l = idx / KW, k3l = idx % KW;
+            if (k4l >= a4l && k4l <= b4l && k3l >= a3l && k3l <= b3l)
+              v = rp.U3[((u3base + xg) * nK4 + k4g0 + k4l) * nK3 + k3g0 + k3l];
+            U3s[idx] = v;
+          } else if (idx < n_u3 + n_u2) {
+            const int q = idx - n_u3, o = q / (8 * KW), k5i = (q / KW) % 8, k4l = q % KW;
+            const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o];
+            const int b5 = imax(lo5, x14lo), e5 = imin(lo5 + 2 * (n5 - 1), x14hi);
+            const int k5 = b5 + 2 * k5i;
+            if (n5 > 0 && k5 <= e5 && k4l >= a4l && k4l <= b4l)
+              v = rp.U2[((((int64_t)o35 * nd + o) * NX + xg) * nK5 + (k5 - rp.K_lo2[3]) / 2) * nK4 +
+                        k4g0 + k4l];
+            U2s[q] = v;
+          } else if (idx < n_u3 + n_u2 + n_u4) {
+            const int q = idx - n_u3 - n_u2, o = q / (KW * 8), k3l = (q / 8) % KW, k2i = q % 8;
+            const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o];
+            const int b2 = imax(lo2, x13lo), e2 = imin(lo2 + 2 * (n2 - 1), x13hi);
+            const int k2 = b2 + 2 * k2i;
+            if (n2 > 0 && k2 <= e2 && k3l >= a3l && k3l <= b3l)
+              v = rp.U4[((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g0 + k3l) * nK2 +
+                        (k2 - rp.K_lo2[0]) / 2];
+            U4s[q] = v;
+          } else {
+            const int q = idx - n_u3 - n_u2 - n_u4, side = q / (nd * 8), o = (q / 8) % nd, i = q % 8;
+            if (side == 0) {  // U1 for the active k5 of l45 = o
+              const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o];
+              const int b5 = imax(lo5, x14lo), e5 = imin(lo5 + 2 * (n5 - 1), x14hi);
+              const int k5 = b5 + 2 * i;
+              if (n5 > 0 && k5 <= e5)
+                v = rp.U1[(((int64_t)o25 * NX + xg) * d1 + n1) * nK5 + (k5 - rp.K_lo2[3]) / 2];
+              U1s[o * 8 + i] = v;
+            } else {  // U5 for the active k2 of l23 = o
+              const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o];
+              const int b2 = imax(lo2, x13lo), e2 = imin(lo2 + 2 * (n2 - 1), x13hi);
+              const int k2 = b2 + 2 * i;
+              if (n2 > 0 && k2 <= e2)
+                v = rp.U5[(((int64_t)o25 * NX + xg) * nK2 + (k2 - rp.K_lo2[0]) / 2) * d1 + n1];
+              U5s[o * 8 + i] = v;
+            }
+          }
         }
-        U3s[idx] = v;
       }
+      __syncthreads();
       // Half chains.  KW = 16: G on threads 0..127 and H on 128..255 at the same time.
       for (int pass = 0; pass < (KW == 16 ? 1 : 2); ++pass) {
         const bool doG = KW == 16 ? tid < 128 : pass == 0;
@@ -144,21 +193,21 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, dou
 #pragma unroll
           for (int q = 0; q < 8; ++q) g[q] = 0.0;
           if (k4l >= a4l && k4l <= b4l) {
-            const int k4 = w4lo + 2 * k4l, k4g = (k4 - rp.K_lo2[2]) / 2;
-            const int k5a = iabs(x - J[L14]), k5b = x + J[L14];
+            const int k4 = w4lo + 2 * k4l;
             for (int o = 0; o < nd; ++o) {
               const int n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
               if (n5 == 0 || k4 < lo4 || k4 > lo4 + 2 * (n4 - 1)) continue;
+              // active k5 of this l45: its range intersected with the (k5 j14 x) triad
               const int lo5 = rng[0 * nd + o];
-              const int ka = imax(lo5, k5a), kb = imin(lo5 + 2 * (n5 - 1), k5b);
-              const double *m5 = Mb + (0 * nd + o) * 64 + i5 * 8;
-              const double *u1 = rp.U1 + (((int64_t)o25 * NX + xg) * d1 + n1) * nK5;
-              const double *u2 = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5) * nK4 + k4g;
+              const int b5 = imax(lo5, x14lo), e5 = imin(lo5 + 2 * (n5 - 1), x14hi);
+              const int c5 = e5 >= b5 ? (e5 - b5) / 2 + 1 : 0;
+              const double *m5 = Mb + (0 * nd + o) * 64 + i5 * 8 + (b5 - lo5) / 2;
+              const double *u2 = U2s + o * 8 * KW + k4l;
+              const double *u1 = U1s + o * 8;
               double t = 0.0;
-              for (int k5 = ka; k5 <= kb; k5 += 2) {
-                const int k5g = (k5 - rp.K_lo2[3]) / 2;
-                t += u1[k5g] * m5[(k5 - lo5) / 2] * u2[(int64_t)k5g * nK4];
-              }
+#pragma unroll
+              for (int k5i = 0; k5i < 8; ++k5i)
+                if (k5i < c5) t += u1[k5i] * m5[k5i] * u2[k5i * KW];
               const double *m4 = Mb + (1 * nd + o) * 64 + (k4 - lo4) / 2;
 #pragma unroll
               for (int i4 = 0; i4 < 8; ++i4) g[i4] += t * m4[i4 * 8];
@@ -172,21 +221,20 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, dou
 #pragma unroll
           for (int q = 0; q < 8; ++q) hq[q] = 0.0;
           if (k3l >= a3l && k3l <= b3l) {
-            const int k3 = w3lo + 2 * k3l, k3g = (k3 - rp.K_lo2[1]) / 2;
-            const int k2a = iabs(J[L13] - x), k2b = J[L13] + x;
+            const int k3 = w3lo + 2 * k3l;
             for (int o = 0; o < nd; ++o) {
               const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o];
               const int lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
               if (n2 == 0 || k3 < lo3 || k3 > lo3 + 2 * (n3 - 1)) continue;
-              const int ka = imax(lo2, k2a), kb = imin(lo2 + 2 * (n2 - 1), k2b);
-              const double *m2 = Mb + (2 * nd + o) * 64 + i2 * 8;
-              const double *u4 = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g) * nK2;
-              const double *u5 = rp.U5 + (((int64_t)o25 * NX + xg) * nK2) * d1 + n1;
+              const int b2 = imax(lo2, x13lo), e2 = imin(lo2 + 2 * (n2 - 1), x13hi);
+              const int c2 = e2 >= b2 ? (e2 - b2) / 2 + 1 : 0;
+              const double *m2 = Mb + (2 * nd + o) * 64 + i2 * 8 + (b2 - lo2) / 2;
+              const double *u4 = U4s + (o * KW + k3l) * 8;
+              const double *u5 = U5s + o * 8;
               double t = 0.0;
-              for (int k2 = ka; k2 <= kb; k2 += 2) {
-                const int k2g = (k2 - rp.K_lo2[0]) / 2;
-                t += u4[k2g] * m2[(k2 - lo2) / 2] * u5[(int64_t)k2g * d1];
-              }
+#pragma unroll
+              for (int k2i = 0; k2i < 8; ++k2i)
+                if (k2i < c2) t += u4[k2i] * m2[k2i] * u5[k2i];
               const double *m3 = Mb + (3 * nd + o) * 64 + (k3 - lo3) / 2;
 #pragma unroll
               for (int i3 = 0; i3 < 8; ++i3) hq[i3] += t * m3[i3 * 8];
@@ -266,7 +314,8 @@ __global__ __launch_bounds__(RT) void ring_batch_kernel(const RingParams *cfgs, 
 
 size_t ring_smem_bytes(int KW, int nd) {
   const int GS = KW + 1;
-  return sizeof(double) * (size_t)(2 * 64 * GS + KW * 64 + KW * KW + 4 * nd * 64) +
+  return sizeof(double) * (size_t)(2 * 64 * GS + KW * 64 + KW * KW + 4 * nd * 64 +
+                                   2 * nd * 8 * KW + 2 * nd * 8) +
          sizeof(int) * (size_t)(8 * nd);
 }
 
