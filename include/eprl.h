@@ -100,8 +100,10 @@ int eprl_count_terms(const int two_j[10], int dl, int64_t *live_shells, double *
  *   out[1] = FP64 flops of the per-shell order: 2 x (multiply-adds of the four mode products)
  *            + 6 per (term, allowed x) for the {15j} sums;
  *   out[2] = useful FP64 flops of the factorised order (active index ranges only);
- *   out[3] = FP64 flops its matrix-core tiles execute (16x16x4 tiles, padding included). */
-int eprl_count_work(const int two_j[10], int dl, double out[4]);
+ *   out[3] = FP64 flops its matrix-core tiles execute (16x16x4 tiles, padding included);
+ *   out[4] = tile class of the factorised kernel for this configuration (0..7), or -1 when
+ *            the configuration falls back to the per-shell order. */
+int eprl_count_work(const int two_j[10], int dl, double out[5]);
 
 /* The vertex tensor of eq. (vertex-ampl), computed by the framed algorithm of Sec. 3.1:
  * 6j tables (step 4), then per shell the {15j} tensor W (6(i)), the booster sub-matrices

@@ -106,12 +106,14 @@ def count_terms(two_j, dl):
 
 
 def count_work(two_j, dl):
-    """dict: terms, shell_flops, ring_useful_flops, ring_mfma_flops (exact host counts)."""
-    out = (ctypes.c_double * 4)()
+    """dict: terms, shell_flops, ring_useful_flops, ring_mfma_flops (exact host counts) and
+    ring_class (tile class of the factorised kernel, -1 when it does not apply)."""
+    out = (ctypes.c_double * 5)()
     rc = _lib.eprl_count_work(_ints(two_j, 10), int(dl), out)
     if rc:
         raise EprlError(rc, "inadmissible spins or shell count")
-    return {"terms": out[0], "shell_flops": out[1], "ring_useful_flops": out[2], "ring_mfma_flops": out[3]}
+    return {"terms": out[0], "shell_flops": out[1], "ring_useful_flops": out[2],
+            "ring_mfma_flops": out[3], "ring_class": int(out[4])}
 
 
 # ---------------------------------------------------------------- device calls

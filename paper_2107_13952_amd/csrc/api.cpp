@@ -327,7 +327,7 @@ int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int acc
   rp.nchunk = nchunk;
   {
     TimedLaunch tl(c, 4);
-    HIP_TRY(c, launch_ring(rp, p.ring_KW, c->stream));
+    HIP_TRY(c, launch_ring(rp, p.ring_cls, c->stream));
   }
   ReduceParams red = reduce_params(p, rp.partial, nchunk, A, accumulate);
   {
@@ -352,7 +352,7 @@ int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, co
   const bool full = sb == 0 && se == probe.nshell;
   if (c->algo == EPRL_ALGO_RING && (!full || probe.ring_KW == 0))
     return fail(c, EPRL_ERANGE,
-                "the factorised path needs the full shell range, i and k ranges <= 8 and core "
+                "the factorised path needs the full shell range, i and k ranges <= 16 and core "
                 "windows <= 32");
   if (full && c->algo != EPRL_ALGO_SHELL && probe.ring_KW != 0)
     return ring_impl(c, two_j, dl, B, accumulate, A, probe);
@@ -466,7 +466,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   // New batch shape: plan every configuration and lay out the workspace.
   std::vector<BatchEntry> ent(n);
   size_t off = 0;
-  int fact_max = 0, KW = 0, max_nd = 1;
+  int fact_max = 0, max_nd = 1;
   for (int q = 0; q < n; ++q) {
     BatchEntry &b = ent[q];
     std::string err;
@@ -483,10 +483,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
       return fail(c, EPRL_ERANGE, "the factorised path does not apply to every configuration");
     batch_chunks(p, b.ring, b.nchunk, b.chunk);
     fact_max = std::max(fact_max, p.fact_max);
-    if (b.ring) {
-      KW = std::max(KW, p.ring_KW);
-      max_nd = std::max(max_nd, p.nd);
-    }
+    if (b.ring) max_nd = std::max(max_nd, p.nd);
     b.tables = off;
     off += align_up((size_t)p.toff[5] * sizeof(double), 256);
     b.boff = off;
@@ -496,29 +493,38 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     b.partial = off;
     off += align_up((size_t)b.nchunk * p.a_size * sizeof(double), 256);
   }
-  // Work list of the persistent kernel: (configuration, chunk, i1), longest first.
+  // Work lists of the persistent kernels, one per tile class: (configuration, chunk, i1, row
+  // block), longest first.
   struct Item {
     double cost;
-    int cfg, chunk, n1;
+    int cfg, chunk, n1, rb;
   };
-  std::vector<Item> items;
+  std::vector<Item> cls_items[8];
   std::vector<int> ring_index(n, -1);
   int nring = 0;
   for (int q = 0; q < n; ++q) {
     if (!ent[q].ring) continue;
     ring_index[q] = nring++;
-    double w[4];
+    double w[5];
     count_work(ent[q].plan, w);
-    const double per = w[3] / ((double)ent[q].nchunk * ent[q].plan.i[0].n);
+    const int cls = ent[q].plan.ring_cls, nrb = ring_row_blocks(cls);
+    const double per = w[3] / ((double)ent[q].nchunk * ent[q].plan.i[0].n * nrb);
     for (int ch = 0; ch < ent[q].nchunk; ++ch)
-      for (int n1 = 0; n1 < ent[q].plan.i[0].n; ++n1) items.push_back({per, ring_index[q], ch, n1});
+      for (int n1 = 0; n1 < ent[q].plan.i[0].n; ++n1)
+        for (int rb = 0; rb < nrb; ++rb) cls_items[cls].push_back({per, ring_index[q], ch, n1, rb});
   }
-  std::stable_sort(items.begin(), items.end(),
-                   [](const Item &a, const Item &b) { return a.cost > b.cost; });
+  std::vector<Item> items;
+  int cls_begin[9] = {0};
+  for (int cls = 0; cls < 8; ++cls) {
+    std::stable_sort(cls_items[cls].begin(), cls_items[cls].end(),
+                     [](const Item &a, const Item &b) { return a.cost > b.cost; });
+    items.insert(items.end(), cls_items[cls].begin(), cls_items[cls].end());
+    cls_begin[cls + 1] = (int)items.size();
+  }
   const size_t params_off = off;
   off += align_up((size_t)std::max(nring, 1) * sizeof(RingParams), 256);
   const size_t items_off = off;
-  off += align_up(std::max<size_t>(items.size(), 1) * 3 * sizeof(int), 256);
+  off += align_up(std::max<size_t>(items.size(), 1) * 4 * sizeof(int), 256);
   int rc = ensure_fexp(c, fact_max);
   if (rc) return rc;
   // Drop the previous graph and workspace.
@@ -595,11 +601,12 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
       so += ent[q].partial - ent[q].boff;
     }
     std::memcpy(st + so, params.data(), params.size() * sizeof(RingParams));
-    std::vector<int> flat(std::max<size_t>(items.size(), 1) * 3, 0);
+    std::vector<int> flat(std::max<size_t>(items.size(), 1) * 4, 0);
     for (size_t k = 0; k < items.size(); ++k) {
-      flat[3 * k] = items[k].cfg;
-      flat[3 * k + 1] = items[k].chunk;
-      flat[3 * k + 2] = items[k].n1;
+      flat[4 * k] = items[k].cfg;
+      flat[4 * k + 1] = items[k].chunk;
+      flat[4 * k + 2] = items[k].n1;
+      flat[4 * k + 3] = items[k].rb;
     }
     std::memcpy(st + so + (items_off - params_off), flat.data(), flat.size() * sizeof(int));
     so = 0;
@@ -630,11 +637,13 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     e = ent[q].ring ? launch_ring_tables(tp, ent[q].plan.toff[5], c->stream)
                     : launch_sixj_tables(tp, ent[q].plan.toff[5], c->stream);
   }
-  if (e == hipSuccess && nring > 0) {
-    const int grid = (int)std::min<size_t>(items.size(), (size_t)ncu * 4);
+  for (int cls = 0; cls < 8 && e == hipSuccess; ++cls) {
+    const int nit = cls_begin[cls + 1] - cls_begin[cls];
+    if (nit == 0) continue;
+    const int grid = (int)std::min<int>(nit, ncu * 4);
     e = launch_ring_batch(reinterpret_cast<const RingParams *>(ws + params_off),
-                          reinterpret_cast<const int *>(ws + items_off), (int)items.size(), KW,
-                          max_nd, grid, c->stream);
+                          reinterpret_cast<const int *>(ws + items_off) + 4 * cls_begin[cls], nit,
+                          cls, max_nd, grid, c->stream);
   }
   for (int q = 0; q < n && e == hipSuccess; ++q) {
     if (ent[q].ring) continue;
@@ -759,7 +768,7 @@ int eprl_count_terms(const int two_j[10], int dl, int64_t *live_shells, double *
   return EPRL_OK;
 }
 
-int eprl_count_work(const int two_j[10], int dl, double out[4]) {
+int eprl_count_work(const int two_j[10], int dl, double out[5]) {
   if (!out) return EPRL_EINVAL;
   Plan p;
   std::string err;

@@ -43,6 +43,8 @@ struct Plan {
   // them to fit its KW-wide LDS tiles, and all i and k ranges to fit 8.
   int ring_w4 = 0, ring_w3 = 0;
   int ring_KW = 0;            // 16 or 32 when the ring path applies, else 0
+  int ring_DI = 0, ring_DK = 0;  // padded boundary / virtual intertwiner tile sizes (8 or 16)
+  int ring_cls = -1;          // tile class of the ring kernel, -1 when it does not apply
 };
 
 // Build a plan; returns EPRL_OK or an error code with a message in `err`.
@@ -50,7 +52,7 @@ int make_plan(const int two_j[10], int dl, Plan &p, std::string &err);
 // Live-shell and term counts (host enumeration).
 void count_terms(const Plan &p, int64_t &live, double &terms);
 // Exact work counts: terms, per-shell-order flops, factorised-order useful and executed flops.
-void count_work(const Plan &p, double out[4]);
+void count_work(const Plan &p, double out[5]);
 // Primes up to n.
 std::vector<int> primes_upto(int n);
 
@@ -117,12 +119,14 @@ hipError_t launch_sixj_batch(const int *args, int n, double *out, const uint16_t
                              const int *primes, int nprime, int fact_max, hipStream_t s);
 hipError_t launch_assemble(const VertexParams &vp, int D, hipStream_t s);
 hipError_t launch_reduce(const ReduceParams &rp, hipStream_t s);
-size_t ring_smem_bytes(int KW, int nd);
+int ring_class(int DI, int DK, int KW);
+int ring_row_blocks(int cls);
+size_t ring_smem_bytes(int cls, int nd);
 // Largest dl + 1 the ring kernels stage booster blocks for.
 constexpr int kRingMaxNd = 16;
 hipError_t ring_init_attributes();
-hipError_t launch_ring(const RingParams &rp, int KW, hipStream_t s);
-hipError_t launch_ring_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems, int KW,
+hipError_t launch_ring(const RingParams &rp, int cls, hipStream_t s);
+hipError_t launch_ring_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems, int cls,
                              int max_nd, int grid, hipStream_t s);
 hipError_t launch_shell_fifteenj(const VertexParams &vp, int64_t shell, double *W,
                                  hipStream_t s);

@@ -195,10 +195,14 @@ int make_plan(const int two_j[10], int dl, Plan &p, std::string &err) {
       if (hi3 >= 0) p.ring_w3 = std::max(p.ring_w3, (hi3 - lo3) / 2 + 1);
     }
   }
-  int ring_dmax = p.kmax;
-  for (int e = 0; e < 5; ++e) ring_dmax = std::max(ring_dmax, p.i[e].n);
+  int imaxn = 0;
+  for (int e = 0; e < 5; ++e) imaxn = std::max(imaxn, p.i[e].n);
   const int w = std::max(p.ring_w4, p.ring_w3);
-  p.ring_KW = (ring_dmax > 8 || nd > kRingMaxNd) ? 0 : (w <= 16 ? 16 : (w <= 32 ? 32 : 0));
+  p.ring_DI = imaxn <= 8 ? 8 : (imaxn <= 16 ? 16 : 0);
+  p.ring_DK = p.kmax <= 8 ? 8 : (p.kmax <= 16 ? 16 : 0);
+  p.ring_KW = w <= 16 ? 16 : (w <= 32 ? 32 : 0);
+  if (p.ring_DI == 0 || p.ring_DK == 0 || p.ring_KW == 0 || nd > kRingMaxNd) p.ring_KW = 0;
+  p.ring_cls = p.ring_KW ? ring_class(p.ring_DI, p.ring_DK, p.ring_KW) : -1;
   return EPRL_OK;
 }
 
@@ -247,7 +251,7 @@ int triad_count(int lo, int n, int a, int x) {
 
 }  // namespace
 
-void count_work(const Plan &p, double out[4]) {
+void count_work(const Plan &p, double out[5]) {
   const int nd = p.nd, nd3 = nd * nd * nd;
   const int *J = p.two_j;
   const int d1 = p.i[0].n, d2 = p.i[1].n, d3 = p.i[2].n, d4 = p.i[3].n, d5 = p.i[4].n;
@@ -287,6 +291,8 @@ void count_work(const Plan &p, double out[4]) {
   // kernel evaluates them: per (core, i1, x) with non-empty active k4 and k3 windows.
   double useful = 0, executed = 0;
   const int KW = p.ring_KW > 0 ? p.ring_KW : 16;
+  const int DI = p.ring_DI > 0 ? p.ring_DI : 8;
+  const double rows = (double)DI * DI, cols = (double)DI * DI;  // padded tile rows / columns
   for (int o24 = 0; o24 < nd; ++o24)
     for (int o25 = 0; o25 < nd; ++o25)
       for (int o34 = 0; o34 < nd; ++o34)
@@ -342,12 +348,13 @@ void count_work(const Plan &p, double out[4]) {
               useful += 2.0 * d5 * d4 * na4 * na3 + 2.0 * d5 * d4 * na3 * d3 * d2;
               const int s4 = ((b4 - w4lo) / 2) / 4 - ((a4 - w4lo) / 2) / 4 + 1;
               const int s3 = ((b3 - w3lo) / 2) / 4 - ((a3 - w3lo) / 2) / 4 + 1;
-              executed += 2.0 * 64 * KW * 4 * s4 + 2.0 * 64 * 64 * 4 * s3;
+              executed += 2.0 * rows * KW * 4 * s4 + 2.0 * rows * cols * 4 * s3;
             }
           }
         }
   out[2] = useful;
   out[3] = executed;
+  out[4] = p.ring_cls;
 }
 
 }  // namespace eprl
