@@ -163,7 +163,8 @@ def main():
             dd, _, oo = lib.layout(tj, d)
             sh = [(dd[e + 1], int((oo[e * (d + 1) ** 3 + t + 1] - oo[e * (d + 1) ** 3 + t]) // dd[e + 1]))
                   for e in range(4) for t in range((d + 1) ** 3)]
-            bl.append(torch.from_numpy(workloads.synthetic_boosters(1003 + 1000 + c, sh)).to(dev))
+            bl.append(torch.from_numpy(workloads.synthetic_boosters(
+            workloads.batch_booster_seed(workloads.CFG3_SEED, c), sh)).to(dev))
         bterms = sum(lib.count_terms(tj, d)[1] for tj, d in configs)
         progress(f"batched workload: {len(configs)} configurations, {bterms:.3g} terms")
         outs = lib.vertex_tensor_batched(configs, 1.2, bl)

@@ -56,9 +56,14 @@ def grad_psi(a, psis):
     return out
 
 
-def grad_boosters(two_j, dl, boosters, psis):
-    """dF/dB for every packed booster entry (complex, same packing as the input)."""
+def grad_boosters(two_j, dl, boosters, psis, only=None):
+    """dF/dB for every packed booster entry (complex, same packing as the input).
+
+    ``only``: a list of booster blocks (edge e in 2..5, triple index t); then only the shells
+    that use one of them are visited and a dict {(e, t): dF/dB block} is returned.
+    """
     blocks = unpack_boosters(two_j, dl, boosters)
+    wanted = None if only is None else {(int(e), int(t)) for e, t in only}
     bnd = R.boundary_ranges(two_j)
     psit = [np.asarray(p, dtype=np.complex128) * np.sqrt(lo + 2 * np.arange(n) + 1.0)
             for p, (lo, n) in zip(psis, bnd)]
@@ -68,8 +73,10 @@ def grad_boosters(two_j, dl, boosters, psis):
         kr = [R.virtual_range(two_l, e) for e in range(2, 6)]
         if any(d == 0 for _, d in kr):
             continue
-        w = fifteenj_block(bnd[0], kr, two_l).astype(np.complex128)   # W[i1, k2, k3, k4, k5]
         keys = {e: (e, R.edge_triple_index(e, shell, dl)) for e in range(2, 6)}
+        if wanted is not None and not wanted.intersection(keys.values()):
+            continue
+        w = fifteenj_block(bnd[0], kr, two_l).astype(np.complex128)   # W[i1, k2, k3, k4, k5]
         weights = {e: (kr[e - 2][0] + 2 * np.arange(kr[e - 2][1]) + 1.0) for e in range(2, 6)}
         v = {e: psit[e - 1] @ (blocks[keys[e]] * weights[e][None, :]) for e in range(2, 6)}
         t = np.einsum("abcde,a->bcde", w, psit[0])                     # [k2, k3, k4, k5]
@@ -81,5 +88,7 @@ def grad_boosters(two_j, dl, boosters, psis):
         }
         for e in range(2, 6):
             grads[keys[e]] += np.outer(psit[e - 1], weights[e] * g[e])
+    if wanted is not None:
+        return {key: grads[key] for key in sorted(wanted)}
     return np.concatenate([grads[(e, t)].ravel() for e in range(2, 6)
                            for t in range((dl + 1) ** 3)])

@@ -51,17 +51,22 @@ def _weighted(block, two_klo):
     return block * (ks + 1)[None, :]
 
 
-def shell_contribution(two_j, dl, blocks, shell):
+def shell_contribution(two_j, dl, blocks, shell, i1_rows=None):
     """The contracted {15j} x booster term of one shell, indexed [i1, i2, i3, i4, i5].
 
-    Returns None for a shell with an empty virtual-intertwiner range.
+    ``i1_rows`` (indices into the i1 range) restricts the result to those rows of the gauge-fixed
+    intertwiner, in the given order.  Returns None for a shell with an empty virtual-intertwiner
+    range.
     """
     two_l = R.shell_spins(two_j, shell)
     kr = [R.virtual_range(two_l, e) for e in range(2, 6)]
     if any(d == 0 for _, d in kr):
         return None
     i1r = R.boundary_ranges(two_j)[0]
-    w = fifteenj_block(i1r, kr, two_l)                            # W[i1, k2, k3, k4, k5]
+    if i1_rows is None:
+        w = fifteenj_block(i1r, kr, two_l)                        # W[i1, k2, k3, k4, k5]
+    else:
+        w = np.concatenate([fifteenj_block((i1r[0] + 2 * n, 1), kr, two_l) for n in i1_rows])
     m = {e: _weighted(blocks[(e, R.edge_triple_index(e, shell, dl))], kr[e - 2][0])
          for e in range(2, 6)}
     # Contract one virtual intertwiner at a time: k5, then k4, k3, k2.
@@ -78,20 +83,27 @@ def _normalisation(two_j):
     return np.einsum("a,b,c,d,e->abcde", *vecs)
 
 
-def vertex_tensor(two_j, dl, boosters, shells=None, normalise=True):
+def vertex_tensor(two_j, dl, boosters, shells=None, normalise=True, i1_rows=None):
     """FP64 vertex tensor A[i1, i2, i3, i4, i5] (row-major, i5 fastest).
 
     ``boosters`` is the packed buffer of raw B4 values (no dimension factors).  ``shells``
     restricts the sum to a subset of shell tuples (default: all of them); the result is
-    then the partial sum over those shells.
+    then the partial sum over those shells.  ``i1_rows`` computes only those rows of the
+    gauge-fixed intertwiner i1 (a reduced boundary-intertwiner range, Sec. 3.1 and 3.2); the
+    result then has len(i1_rows) rows in that order.
     """
     R.check_spins(two_j, dl)
     blocks = unpack_boosters(two_j, dl, boosters)
     dims = tuple(n for _, n in R.boundary_ranges(two_j))
+    if i1_rows is not None:
+        i1_rows = [int(n) for n in i1_rows]
+        if any(n < 0 or n >= dims[0] for n in i1_rows):
+            raise ValueError("i1 row outside the boundary-intertwiner range")
+        dims = (len(i1_rows),) + dims[1:]
     s = np.zeros(dims)
     c = np.zeros(dims)
     for shell in (R.all_shells(dl) if shells is None else shells):
-        term = shell_contribution(two_j, dl, blocks, shell)
+        term = shell_contribution(two_j, dl, blocks, shell, i1_rows)
         if term is None:
             continue
         # Neumaier compensated summation, elementwise.
@@ -99,7 +111,10 @@ def vertex_tensor(two_j, dl, boosters, shells=None, normalise=True):
         c += np.where(np.abs(s) >= np.abs(term), (s - t) + term, (term - t) + s)
         s = t
     a = s + c
-    return a * _normalisation(two_j) if normalise else a
+    if not normalise:
+        return a
+    norm = _normalisation(two_j)
+    return a * (norm if i1_rows is None else norm[i1_rows])
 
 
 def vertex_tensor_mp(two_j, dl, boosters, dps=30):

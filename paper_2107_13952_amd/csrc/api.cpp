@@ -525,6 +525,8 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   off += align_up((size_t)std::max(nring, 1) * sizeof(RingParams), 256);
   const size_t items_off = off;
   off += align_up(std::max<size_t>(items.size(), 1) * 4 * sizeof(int), 256);
+  const size_t counters_off = off;  // one work-queue counter per tile class
+  off += 256;
   int rc = ensure_fexp(c, fact_max);
   if (rc) return rc;
   // Drop the previous graph and workspace.
@@ -637,13 +639,18 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     e = ent[q].ring ? launch_ring_tables(tp, ent[q].plan.toff[5], c->stream)
                     : launch_sixj_tables(tp, ent[q].plan.toff[5], c->stream);
   }
+  int *counters = reinterpret_cast<int *>(ws + counters_off);
+  if (e == hipSuccess && nring > 0) e = launch_reset_counters(counters, 8, c->stream);
   for (int cls = 0; cls < 8 && e == hipSuccess; ++cls) {
     const int nit = cls_begin[cls + 1] - cls_begin[cls];
     if (nit == 0) continue;
-    const int grid = (int)std::min<int>(nit, ncu * 4);
+    // Enough workgroups to fill the chip at the occupancy the tile class allows.
+    const size_t shm = ring_smem_bytes(cls, max_nd);
+    const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(shm, 1))));
+    const int grid = (int)std::min<int>(nit, ncu * per_cu);
     e = launch_ring_batch(reinterpret_cast<const RingParams *>(ws + params_off),
                           reinterpret_cast<const int *>(ws + items_off) + 4 * cls_begin[cls], nit,
-                          cls, max_nd, grid, c->stream);
+                          cls, max_nd, grid, counters + cls, c->stream);
   }
   for (int q = 0; q < n && e == hipSuccess; ++q) {
     if (ent[q].ring) continue;

@@ -127,7 +127,8 @@ constexpr int kRingMaxNd = 16;
 hipError_t ring_init_attributes();
 hipError_t launch_ring(const RingParams &rp, int cls, hipStream_t s);
 hipError_t launch_ring_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems, int cls,
-                             int max_nd, int grid, hipStream_t s);
+                             int max_nd, int grid, int *next, hipStream_t s);
+hipError_t launch_reset_counters(int *c, int n, hipStream_t s);
 hipError_t launch_shell_fifteenj(const VertexParams &vp, int64_t shell, double *W,
                                  hipStream_t s);
 

@@ -41,16 +41,25 @@ __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 // block rb (rows rb * 64 .. rb * 64 + 63 of A(i1; rows, cols)).
 template <int DI, int DK, int KW>
 __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int rb, double *smem) {
+  constexpr bool STAGE = DI == 8;  // booster blocks of a core staged in LDS (small tiles only)
   constexpr int GS = KW + 1;       // padded row stride of G and P
   constexpr int CC = DI * DI;      // columns (i3, i2)
   constexpr int CT = CC / 16;      // column tiles
   constexpr int IB = 64 / DI;      // i5 values per row block
+  // LDS strides, padded so that the access patterns below spread over the 64 banks.
+  constexpr int HS = CC + 8;                     // row of H
+  constexpr int U3S = KW == 32 ? KW + 8 : KW;    // row of the U3 slice
+  constexpr int T5S = IB * DK + 8;               // one l45 of T5
+  constexpr int T2S = DI * DK + 8;               // one l23 of T2
+  constexpr int MBS = DI * DK + 2;               // one booster block
   const int nd = rp.nd, nd3 = nd * nd * nd;
-  double *Gs = smem;                  // [64][GS]  rows (i5, i4) of this block, cols k4
-  double *Ps = Gs + 64 * GS;          // [64][GS]  rows (i5, i4), cols k3
-  double *Hs = Ps + 64 * GS;          // [KW][CC]  rows k3, cols (i3, i2)
-  double *U3s = Hs + KW * CC;         // [KW][KW]  k4 x k3
-  int64_t *bo = reinterpret_cast<int64_t *>(U3s + KW * KW);  // [4][nd] booster block offsets
+  double *Gs = smem;                  // [64][GS]  rows (i5, i4) of this block: G (cols k4), then P (cols k3)
+  double *Hs = Gs + 64 * GS;          // [KW][HS]  rows k3, cols (i3, i2)
+  double *U3s = Hs + KW * HS;         // [KW][U3S] k4 x k3
+  double *T5 = U3s + KW * U3S;        // [nd][T5S] per l45: sum_k5 U1 M5 U2 as [i5 of block][k4]
+  double *T2 = T5 + nd * T5S;         // [nd][T2S] per l23: sum_k2 U4 M2 U5 as [i2][k3]
+  double *Mb = T2 + nd * T2S;         // [4][nd][MBS] weighted boosters M5, M4, M2, M3 as [i][k] (if STAGE)
+  int64_t *bo = reinterpret_cast<int64_t *>(Mb + (STAGE ? 4 * nd * MBS : 0));  // [4][nd]
   int *rng = reinterpret_cast<int *>(bo + 4 * nd);           // [8][nd] lo/n of k5, k4, k2, k3
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -109,6 +118,20 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
       }
     }
     if (w4hi < 0 || w3hi < 0) continue;  // uniform: no live shell in this core
+    if (STAGE) {
+      // Weighted booster blocks (2k+1) B of this core: e = 0 M5, 1 M4 (per l45), 2 M2, 3 M3
+      // (per l23); rows i, columns k relative to the lowest k of the block.
+      for (int idx = tid; idx < 4 * nd * DI * DK; idx += RT) {
+        const int e = idx / (nd * DI * DK), o = (idx / (DI * DK)) % nd;
+        const int i = (idx / DK) % DI, k = idx % DK;
+        const int lo = rng[(e == 0 ? 0 : e == 1 ? 2 : e == 2 ? 4 : 6) * nd + o];
+        const int kn = rng[(e == 0 ? 1 : e == 1 ? 3 : e == 2 ? 5 : 7) * nd + o];
+        const int ni = e == 0 ? d5 : e == 1 ? d4 : e == 2 ? d2 : d3;
+        double v = 0.0;
+        if (i < ni && k < kn) v = B[bo[e * nd + o] + (int64_t)i * kn + k] * (double)(lo + 2 * k + 1);
+        Mb[(e * nd + o) * MBS + i * DK + k] = v;
+      }
+    }
     // x closes (i1 l25 x); the other triads restrict the k ranges at each x.
     const int xlo = imax(iabs(two_i1 - l25), rp.X_lo2), xhi = imin(two_i1 + l25, xhi_g);
     const int64_t u3base = (((int64_t)o24 * nd + o34) * nd + o35) * NX;
@@ -121,18 +144,99 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
       const int a3l = (a3 - w3lo) / 2, b3l = (b3 - w3lo) / 2;
       const int x14lo = iabs(x - J[L14]), x14hi = x + J[L14];
       const int x13lo = iabs(J[L13] - x), x13hi = J[L13] + x;
-      __syncthreads();  // previous x's readers of Gs / Hs / U3s / Ps are done
-      // U3 slice of this x, zero outside the active windows.
-      for (int idx = tid; idx < KW * KW; idx += RT) {
-        const int k4l = idx / KW, k3l = idx % KW;
-        double v = 0.0;
-        if (k4l >= a4l && k4l <= b4l && k3l >= a3l && k3l <= b3l) {
+      __syncthreads();  // previous x's readers of Gs / Hs / U3s are done
+      // U3 slice of this x, zero outside the active windows: loaded into registers here and
+      // stored to LDS after step 1, so that its loads and those of step 1 are in flight together.
+      constexpr int NU3 = (KW * KW + RT - 1) / RT;
+      double u3v[NU3];
+#pragma unroll
+      for (int q = 0; q < NU3; ++q) {
+        const int idx = tid + q * RT, k4l = idx / KW, k3l = idx % KW;
+        u3v[q] = 0.0;
+        if (idx < KW * KW && k4l >= a4l && k4l <= b4l && k3l >= a3l && k3l <= b3l) {
           const int k4g = (w4lo - rp.K_lo2[2]) / 2 + k4l, k3g = (w3lo - rp.K_lo2[1]) / 2 + k3l;
-          v = rp.U3[((u3base + xg) * nK4 + k4g) * nK3 + k3g];
+          u3v[q] = rp.U3[((u3base + xg) * nK4 + k4g) * nK3 + k3g];
         }
-        U3s[idx] = v;
       }
-      // Half chains: items u < IB*KW are G entries (i5, k4), the rest H entries (k3, i2).
+      // Half chains, step 1: one item per (l45, k4) and per (l23, k3) reads its 6j column
+      // once for the whole workgroup:
+      //   T5(l45; i5, k4) = sum_k5 U1(k5) M5(i5, k5) U2(k5, k4)      (k5 active at this x)
+      //   T2(l23; k3, i2) = sum_k2 U4(k3, k2) M2(i2, k2) U5(k2)      (k2 active at this x)
+      for (int u = tid; u < 2 * nd * DK; u += RT) {
+        const int side = u / (nd * DK), o = (u / DK) % nd, ki = u % DK;
+        double a[DK], b[DK];
+        if (side == 0) {
+          const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
+          const int k4 = lo4 + 2 * ki;
+          const int ka = imax(lo5, x14lo), kb = imin(lo5 + 2 * (n5 - 1), x14hi);
+          const int c5 = (n5 > 0 && ki < n4 && k4 >= a4 && k4 <= b4 && kb >= ka) ? (kb - ka) / 2 + 1 : 0;
+          const int g0 = (ka - rp.K_lo2[3]) / 2, kk0 = (ka - lo5) / 2, k4g = (k4 - rp.K_lo2[2]) / 2;
+          const double *u1 = rp.U1 + (((int64_t)o25 * NX + xg) * d1 + n1) * nK5 + g0;
+          const double *u2 = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5 + g0) * nK4 + k4g;
+#pragma unroll
+          for (int q = 0; q < DK; ++q) {
+            a[q] = q < c5 ? u1[q] : 0.0;
+            b[q] = q < c5 ? u2[(int64_t)q * nK4] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < DK; ++q) a[q] *= b[q];
+          for (int i5l = 0; i5l < IB; ++i5l) {
+            const int i5 = rb * IB + i5l;
+            double t = 0.0;
+            if (c5 > 0 && i5 < d5) {
+              if (STAGE) {
+                const double *m5 = Mb + (0 * nd + o) * MBS + i5 * DK + kk0;
+#pragma unroll
+                for (int q = 0; q < DK; ++q)
+                  if (q < c5) t += a[q] * m5[q];
+              } else {
+                const double *m5 = B + bo[0 * nd + o] + (int64_t)i5 * n5 + kk0;
+#pragma unroll
+                for (int q = 0; q < DK; ++q)
+                  if (q < c5) t += a[q] * (m5[q] * (double)(ka + 2 * q + 1));
+              }
+            }
+            T5[o * T5S + i5l * DK + ki] = t;
+          }
+        } else {
+          const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
+          const int k3 = lo3 + 2 * ki;
+          const int ka = imax(lo2, x13lo), kb = imin(lo2 + 2 * (n2 - 1), x13hi);
+          const int c2 = (n2 > 0 && ki < n3 && k3 >= a3 && k3 <= b3 && kb >= ka) ? (kb - ka) / 2 + 1 : 0;
+          const int g0 = (ka - rp.K_lo2[0]) / 2, kk0 = (ka - lo2) / 2, k3g = (k3 - rp.K_lo2[1]) / 2;
+          const double *u4 = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g) * nK2 + g0;
+          const double *u5 = rp.U5 + (((int64_t)o25 * NX + xg) * nK2 + g0) * d1 + n1;
+#pragma unroll
+          for (int q = 0; q < DK; ++q) {
+            a[q] = q < c2 ? u4[q] : 0.0;
+            b[q] = q < c2 ? u5[(int64_t)q * d1] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < DK; ++q) a[q] *= b[q];
+          for (int i2 = 0; i2 < DI; ++i2) {
+            double t = 0.0;
+            if (c2 > 0 && i2 < d2) {
+              if (STAGE) {
+                const double *m2 = Mb + (2 * nd + o) * MBS + i2 * DK + kk0;
+#pragma unroll
+                for (int q = 0; q < DK; ++q)
+                  if (q < c2) t += a[q] * m2[q];
+              } else {
+                const double *m2 = B + bo[2 * nd + o] + (int64_t)i2 * n2 + kk0;
+#pragma unroll
+                for (int q = 0; q < DK; ++q)
+                  if (q < c2) t += a[q] * (m2[q] * (double)(ka + 2 * q + 1));
+              }
+            }
+            T2[o * T2S + i2 * DK + ki] = t;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NU3; ++q)
+        if (tid + q * RT < KW * KW) U3s[((tid + q * RT) / KW) * U3S + (tid + q * RT) % KW] = u3v[q];
+      __syncthreads();
+      // Step 2: G(i5, i4, k4) = sum_l45 T5 M4 and H(k3, i3, i2) = sum_l23 M3 T2.
       for (int u = tid; u < IB * KW + KW * DI; u += RT) {
         if (u < IB * KW) {
           const int i5l = u / KW, k4l = u % KW, i5 = rb * IB + i5l;
@@ -140,34 +244,23 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
 #pragma unroll
           for (int q = 0; q < DI; ++q) g[q] = 0.0;
           if (k4l >= a4l && k4l <= b4l && i5 < d5) {
-            const int k4 = w4lo + 2 * k4l, k4g = (k4 - rp.K_lo2[2]) / 2;
+            const int k4 = w4lo + 2 * k4l;
             for (int o = 0; o < nd; ++o) {
               const int n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
               if (n5 == 0 || k4 < lo4 || k4 > lo4 + 2 * (n4 - 1)) continue;
-              const int lo5 = rng[0 * nd + o];
-              const int ka = imax(lo5, x14lo), kb = imin(lo5 + 2 * (n5 - 1), x14hi);
-              const int c5 = kb >= ka ? (kb - ka) / 2 + 1 : 0;  // <= DK
-              const int g0 = (ka - rp.K_lo2[3]) / 2, kk0 = (ka - lo5) / 2;
-              const double *u1 = rp.U1 + (((int64_t)o25 * NX + xg) * d1 + n1) * nK5 + g0;
-              const double *u2 = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5 + g0) * nK4 + k4g;
-              const double *m5 = B + bo[0 * nd + o] + (int64_t)i5 * n5 + kk0;
-              // All loads of this l45 are independent: issue them together.
-              double a1[DK], a2[DK], am[DK];
+              const int k4i = (k4 - lo4) / 2;
+              const double t = T5[o * T5S + i5l * DK + k4i];
+              if (STAGE) {
+                const double *m4 = Mb + (1 * nd + o) * MBS + k4i;
 #pragma unroll
-              for (int q = 0; q < DK; ++q) {
-                a1[q] = q < c5 ? u1[q] : 0.0;
-                a2[q] = q < c5 ? u2[(int64_t)q * nK4] : 0.0;
-                am[q] = q < c5 ? m5[q] * (double)(ka + 2 * q + 1) : 0.0;
+                for (int i4 = 0; i4 < DI; ++i4) g[i4] += t * m4[i4 * DK];
+              } else {
+                const double w4 = (double)(k4 + 1);
+                const double *m4 = B + bo[1 * nd + o] + k4i;
+#pragma unroll
+                for (int i4 = 0; i4 < DI; ++i4)
+                  if (i4 < d4) g[i4] += t * (m4[(int64_t)i4 * n4] * w4);
               }
-              double t = 0.0;
-#pragma unroll
-              for (int q = 0; q < DK; ++q) t += a1[q] * am[q] * a2[q];
-              const int kk4 = (k4 - lo4) / 2;
-              const double w4 = (double)(k4 + 1);
-              const double *m4 = B + bo[1 * nd + o] + kk4;
-#pragma unroll
-              for (int i4 = 0; i4 < DI; ++i4)
-                if (i4 < d4) g[i4] += t * (m4[(int64_t)i4 * n4] * w4);
             }
           }
 #pragma unroll
@@ -178,64 +271,59 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
 #pragma unroll
           for (int q = 0; q < DI; ++q) hq[q] = 0.0;
           if (k3l >= a3l && k3l <= b3l && i2 < d2) {
-            const int k3 = w3lo + 2 * k3l, k3g = (k3 - rp.K_lo2[1]) / 2;
+            const int k3 = w3lo + 2 * k3l;
             for (int o = 0; o < nd; ++o) {
-              const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o];
-              const int lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
+              const int n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
               if (n2 == 0 || k3 < lo3 || k3 > lo3 + 2 * (n3 - 1)) continue;
-              const int ka = imax(lo2, x13lo), kb = imin(lo2 + 2 * (n2 - 1), x13hi);
-              const int c2 = kb >= ka ? (kb - ka) / 2 + 1 : 0;  // <= DK
-              const int g0 = (ka - rp.K_lo2[0]) / 2, kk0 = (ka - lo2) / 2;
-              const double *u4 = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g) * nK2 + g0;
-              const double *u5 = rp.U5 + (((int64_t)o25 * NX + xg) * nK2 + g0) * d1 + n1;
-              const double *m2 = B + bo[2 * nd + o] + (int64_t)i2 * n2 + kk0;
-              double a4[DK], a5[DK], am[DK];
+              const int k3i = (k3 - lo3) / 2;
+              const double t = T2[o * T2S + i2 * DK + k3i];
+              if (STAGE) {
+                const double *m3 = Mb + (3 * nd + o) * MBS + k3i;
 #pragma unroll
-              for (int q = 0; q < DK; ++q) {
-                a4[q] = q < c2 ? u4[q] : 0.0;
-                a5[q] = q < c2 ? u5[(int64_t)q * d1] : 0.0;
-                am[q] = q < c2 ? m2[q] * (double)(ka + 2 * q + 1) : 0.0;
+                for (int i3 = 0; i3 < DI; ++i3) hq[i3] += t * m3[i3 * DK];
+              } else {
+                const double w3 = (double)(k3 + 1);
+                const double *m3 = B + bo[3 * nd + o] + k3i;
+#pragma unroll
+                for (int i3 = 0; i3 < DI; ++i3)
+                  if (i3 < d3) hq[i3] += t * (m3[(int64_t)i3 * n3] * w3);
               }
-              double t = 0.0;
-#pragma unroll
-              for (int q = 0; q < DK; ++q) t += a4[q] * am[q] * a5[q];
-              const int kk3 = (k3 - lo3) / 2;
-              const double w3 = (double)(k3 + 1);
-              const double *m3 = B + bo[3 * nd + o] + kk3;
-#pragma unroll
-              for (int i3 = 0; i3 < DI; ++i3)
-                if (i3 < d3) hq[i3] += t * (m3[(int64_t)i3 * n3] * w3);
             }
           }
 #pragma unroll
-          for (int i3 = 0; i3 < DI; ++i3) Hs[k3l * CC + i3 * DI + i2] = hq[i3];
+          for (int i3 = 0; i3 < DI; ++i3) Hs[k3l * HS + i3 * DI + i2] = hq[i3];
         }
       }
       __syncthreads();
-      // P = G U3 (rows (i5, i4) of this block, cols k3): wavefront `wave` owns row tile `wave`.
+      // P = G U3 (rows (i5, i4) of this block, cols k3): wavefront `wave` owns row tile `wave`
+      // and reads and writes only those rows, so P replaces G in place with no barrier (LDS
+      // operations of one wavefront complete in order).
       {
         const int r = wave * 16 + (lane & 15), kq = lane >> 4;
+        d4v c[KW / 16];
 #pragma unroll
         for (int cb = 0; cb < KW / 16; ++cb) {
-          d4v c = {0.0, 0.0, 0.0, 0.0};
+          c[cb] = d4v{0.0, 0.0, 0.0, 0.0};
           for (int ks = a4l & ~3; ks <= b4l; ks += 4) {
             const double a = Gs[r * GS + ks + kq];
-            const double b = U3s[(ks + kq) * KW + cb * 16 + (lane & 15)];
-            c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+            const double b = U3s[(ks + kq) * U3S + cb * 16 + (lane & 15)];
+            c[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c[cb], 0, 0, 0);
           }
-#pragma unroll
-          for (int j = 0; j < 4; ++j) Ps[(wave * 16 + 4 * kq + j) * GS + cb * 16 + (lane & 15)] = c[j];
         }
+#pragma unroll
+        for (int cb = 0; cb < KW / 16; ++cb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) Gs[(wave * 16 + 4 * kq + j) * GS + cb * 16 + (lane & 15)] = c[cb][j];
+        __builtin_amdgcn_wave_barrier();  // keeps the reads below after these writes
       }
-      __syncthreads();
       // A(i1; rows, cols) += P H over the active k3 window.
       {
         const int r = wave * 16 + (lane & 15), kq = lane >> 4;
         for (int ks = a3l & ~3; ks <= b3l; ks += 4) {
-          const double a = Ps[r * GS + ks + kq];
+          const double a = Gs[r * GS + ks + kq];
 #pragma unroll
           for (int cb = 0; cb < CT; ++cb) {
-            const double b = Hs[(ks + kq) * CC + cb * 16 + (lane & 15)];
+            const double b = Hs[(ks + kq) * HS + cb * 16 + (lane & 15)];
             acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
           }
         }
@@ -269,20 +357,37 @@ __global__ __launch_bounds__(RT) void ring_kernel(RingParams rp) {
 // assignment of items to workgroups (and every partial sum) is fixed.
 template <int DI, int DK, int KW>
 __global__ __launch_bounds__(RT) void ring_batch_kernel(const RingParams *cfgs, const int *items,
-                                                        int nitems) {
+                                                        int nitems, int *next) {
   extern __shared__ double smem[];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  __shared__ int it_s;
+  // Items are taken from a counter in list order (longest first); which workgroup runs an
+  // item does not matter for the result: every item writes its own partial slice.  The loop
+  // ends for every workgroup once the counter passes nitems.
+  for (;;) {
+    if (threadIdx.x == 0) it_s = atomicAdd(next, 1);
+    __syncthreads();
+    const int it = it_s;
+    __syncthreads();
+    if (it >= nitems) break;
     const int *p = items + 4 * it;
     ring_item<DI, DK, KW>(cfgs[p[0]], p[1], p[2], p[3], smem);
   }
 }
 
+// Resets the work-queue counters of a batch (a kernel, so that graph replays start from 0).
+__global__ void reset_counters(int *c, int n) {
+  if (threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
 template <int DI, int DK, int KW>
 struct RingVariant {
-  static size_t smem(int nd) {
-    return sizeof(double) * (size_t)(2 * 64 * (KW + 1) + KW * DI * DI + KW * KW) +
+  static constexpr size_t smem(int nd) {
+    const size_t stage = DI == 8 ? (size_t)4 * nd * (DI * DK + 2) : 0;
+    return sizeof(double) * ((size_t)(64 * (KW + 1) + KW * (DI * DI + 8) + KW * (KW == 32 ? KW + 8 : KW)) +
+                             (size_t)nd * ((64 / DI + DI) * DK + 16) + stage) +
            sizeof(int64_t) * (size_t)(4 * nd) + sizeof(int) * (size_t)(8 * nd);
   }
+  static_assert(smem(kRingMaxNd) <= 160 * 1024, "ring tile class exceeds the LDS of a CU");
   static hipError_t init() {
     const int bytes = (int)smem(kRingMaxNd);
     hipError_t e = hipFuncSetAttribute((const void *)ring_kernel<DI, DK, KW>,
@@ -297,8 +402,8 @@ struct RingVariant {
     return hipGetLastError();
   }
   static hipError_t launch_batch(const RingParams *cfgs, const int *items, int nitems, int max_nd,
-                                 int grid, hipStream_t s) {
-    ring_batch_kernel<DI, DK, KW><<<grid, RT, smem(max_nd), s>>>(cfgs, items, nitems);
+                                 int grid, int *next, hipStream_t s) {
+    ring_batch_kernel<DI, DK, KW><<<grid, RT, smem(max_nd), s>>>(cfgs, items, nitems, next);
     return hipGetLastError();
   }
 };
@@ -352,11 +457,16 @@ hipError_t launch_ring(const RingParams &rp, int cls, hipStream_t s) {
 }
 
 hipError_t launch_ring_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems, int cls,
-                             int max_nd, int grid, hipStream_t s) {
+                             int max_nd, int grid, int *next, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   return dispatch(cls, [&](auto v) {
-    return decltype(v)::launch_batch(cfgs_dev, items_dev, nitems, max_nd, grid, s);
+    return decltype(v)::launch_batch(cfgs_dev, items_dev, nitems, max_nd, grid, next, s);
   });
+}
+
+hipError_t launch_reset_counters(int *c, int n, hipStream_t s) {
+  reset_counters<<<1, 64, 0, s>>>(c, n);
+  return hipGetLastError();
 }
 
 }  // namespace eprl

@@ -1,13 +1,16 @@
 """Write oracle vertex tensors used by the full-size parity tests.
 
 Calls only the oracle and the seeded input generators.  Output: ``vertex_<name>.npz`` with the
-spins, the shell count, the booster seed and A[i1..i5] (float64).  The shell sum is split over
-worker processes by contiguous shell ranges and the partial tensors are summed in range order.
+spins, dl, the booster seed, the i1 rows computed (all of them unless a reduced boundary-
+intertwiner range is asked for) and A[rows, i2..i5] (float64).  The shell sum is split over worker
+processes by contiguous shell ranges and the partial tensors are summed in range order.
 
-    python tests/golden/make_golden.py            # j = 3, dl = 8 (about 4 minutes on 8 cores)
+    python tests/golden/make_golden.py               # every entry of GOLDEN (about 30 min, 8 cores)
+    python tests/golden/make_golden.py j3_dl8 ...     # the named entries only
 """
 import os
 import sys
+import time
 from multiprocessing import Pool
 
 import numpy as np
@@ -15,31 +18,64 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-import workloads  # noqa: E402
+import workloads as W  # noqa: E402
 from oracle import ranges as R  # noqa: E402
 from oracle import vertex as V  # noqa: E402
 
 
+def _batch_entry(name, batch, seed, c, rows=None, dl=None):
+    tj, d = batch[c]
+    return name, dict(two_j=list(tj), dl=d if dl is None else dl,
+                      booster_seed=W.batch_booster_seed(seed, c), rows=rows)
+
+
+def _registry():
+    g = {W.CFG2["name"]: dict(two_j=W.CFG2["two_j"], dl=W.CFG2["dl"], booster_seed=W.CFG2["booster_seed"], rows=None),
+         "j4_dl8": dict(two_j=W.CFG4["two_j"], dl=W.CFG4["dl"], booster_seed=W.CFG4["booster_seed"], rows=None)}
+    b3, b5 = W.cfg3_batch(), W.cfg5_batch()
+    # Irregular batch: the eight configurations with the least work in full, and the four with the
+    # most work on a reduced i1 range (first and last row, or the middle row).
+    for c in (55, 52, 40, 6, 22, 25, 1, 53):
+        g.update([_batch_entry(f"b3_c{c:02d}", b3, W.CFG3_SEED, c)])
+    for c, rows in ((7, [0, 7]), (41, [0, 8]), (0, [4]), (45, [3])):
+        g.update([_batch_entry(f"b3_c{c:02d}_rows", b3, W.CFG3_SEED, c, rows)])
+    # Large spins: two configurations on two i1 rows each, and one at dl = 2 in full.
+    for c, rows in ((0, [0, 10]), (3, [5, 13])):
+        g.update([_batch_entry(f"b5_c{c:02d}_rows", b5, W.CFG5_SEED, c, rows)])
+    g.update([_batch_entry("b5_c00_dl2", b5, W.CFG5_SEED, 0, None, dl=2)])
+    return g
+
+
+GOLDEN = _registry()
+
+
 def _part(args):
-    two_j, dl, seed, lo, hi = args
-    b = workloads.synthetic_boosters(seed, R.block_shapes(two_j, dl))
-    return V.vertex_tensor(two_j, dl, b, shells=R.all_shells(dl)[lo:hi])
+    two_j, dl, seed, rows, lo, hi = args
+    b = W.synthetic_boosters(seed, R.block_shapes(two_j, dl))
+    return V.vertex_tensor(two_j, dl, b, shells=R.all_shells(dl)[lo:hi], i1_rows=rows)
 
 
-def make(cfg, procs=8, pieces=64):
-    two_j, dl, seed = cfg["two_j"], cfg["dl"], cfg["booster_seed"]
+def make(name, procs=8, pieces=64):
+    e = GOLDEN[name]
+    two_j, dl, seed, rows = e["two_j"], e["dl"], e["booster_seed"], e["rows"]
     n = (dl + 1) ** 6
+    pieces = min(pieces, n)
     bounds = [n * q // pieces for q in range(pieces + 1)]
-    jobs = [(two_j, dl, seed, bounds[q], bounds[q + 1]) for q in range(pieces)]
+    jobs = [(two_j, dl, seed, rows, bounds[q], bounds[q + 1]) for q in range(pieces)]
     with Pool(procs) as pool:
         parts = pool.map(_part, jobs)
     a = np.zeros_like(parts[0])
     for p in parts:
         a += p
-    out = os.path.join(HERE, f"vertex_{cfg['name']}.npz")
-    np.savez_compressed(out, two_j=np.array(two_j), dl=dl, booster_seed=seed, A=a)
+    nrow = R.boundary_ranges(two_j)[0][1]
+    out = os.path.join(HERE, f"vertex_{name}.npz")
+    np.savez_compressed(out, two_j=np.array(two_j), dl=dl, booster_seed=seed,
+                        rows=np.arange(nrow) if rows is None else np.array(rows), A=a)
     return out
 
 
 if __name__ == "__main__":
-    print(make(workloads.CFG2))
+    names = sys.argv[1:] or list(GOLDEN)
+    for nm in names:
+        t = time.time()
+        print(make(nm), f"{time.time() - t:.0f} s", flush=True)

@@ -11,6 +11,7 @@ Bars:
 Shell-range partial sums must add up to the full tensor and repeated calls must be bitwise
 identical (fixed-order reductions).
 """
+import os
 import random
 import sys
 
@@ -23,6 +24,9 @@ from oracle import vertex as V
 from oracle import contract as C
 from oracle.fifteenj import fifteenj_block
 from oracle.wigner import sixj, triad
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+from make_golden import GOLDEN  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -223,6 +227,67 @@ def test_cfg2_full_size(lib, torch):
             assert err <= TOL
 
 
+def load_golden(name, required=True):
+    """A stored oracle tensor; a test that needs it is skipped if it has not been written
+    (tests/golden/make_golden.py), one that only uses it as an extra check gets None."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"vertex_{name}.npz")
+    if not os.path.exists(path):
+        if required:
+            pytest.skip(f"stored oracle tensor {name} not written")
+        return None
+    g = np.load(path)
+    e = GOLDEN[name]
+    assert list(g["two_j"]) == list(e["two_j"]) and int(g["dl"]) == e["dl"]
+    assert int(g["booster_seed"]) == e["booster_seed"]
+    return g
+
+
+STORED = [n for n in GOLDEN if n != workloads.CFG2["name"]]
+
+
+@pytest.mark.parametrize("name", STORED)
+def test_stored_oracle_tensor(lib, torch, algo, name):
+    """Irregular spins (every tile class), j = 4 and large-spin vertices at full size against
+    oracle tensors written offline (all i1 rows, or a reduced i1 range for the largest)."""
+    e = GOLDEN[name]
+    g = load_golden(name)
+    b, bd = boosters_for(torch, e["two_j"], e["dl"], e["booster_seed"])
+    note(f"{name} [{algo}] two_j={e['two_j']} dl={e['dl']}")
+    a = vertex_or_skip(lib, algo, e["two_j"], e["dl"], 1.2, bd).cpu().numpy()
+    err = normwise(a[g["rows"]], g["A"])
+    note(f"  normwise error {err:.3e}")
+    assert err <= TOL
+
+
+def test_batched_full_size(lib, torch):
+    """The 64-configuration batch of the benchmark (true dl, 3..10) in one batched call: stored
+    oracle tensors, bitwise equality with plain calls and with a replay of the captured graph."""
+    configs = workloads.cfg3_batch()
+    bds = [boosters_for(torch, tj, dl, workloads.batch_booster_seed(workloads.CFG3_SEED, c))[1]
+           for c, (tj, dl) in enumerate(configs)]
+    note("batched full size: capture")
+    outs = lib.vertex_tensor_batched(configs, 1.2, bds)
+    note("batched full size: replay")
+    again = [torch.empty_like(a) for a in outs]
+    lib.vertex_tensor_batched(configs, 1.2, bds, again)
+    torch.cuda.synchronize()
+    for a, r in zip(outs, again):
+        assert torch.equal(a, r)
+    for name in STORED:
+        if not name.startswith("b3_"):
+            continue
+        c = int(name[4:6])
+        g = load_golden(name, required=False)
+        if g is None:
+            continue
+        err = normwise(outs[c].cpu().numpy()[g["rows"]], g["A"])
+        note(f"  {name} normwise error {err:.3e}")
+        assert err <= TOL
+    for c in (55, 7, 41, 0):
+        tj, dl = configs[c]
+        assert torch.equal(outs[c], lib.vertex_tensor(tj, dl, 1.2, bds[c]))
+
+
 def test_batched_equals_plain(lib, torch):
     configs = workloads.cfg3_batch()[:6]
     configs = [(tj, min(dl, 2)) for tj, dl in configs]
@@ -294,3 +359,74 @@ def test_autograd_against_finite_differences(lib, torch):
                 fd = (L(b, up) - L(b, dn)) / (2 * h)
                 got = gq[n].real if delta == h else gq[n].imag
                 assert abs(fd - got) <= 2e-8 * max(1.0, abs(fd))
+
+
+def _adjoint_full_size(lib, torch, two_j, dl, seed, psi_seed, golden, sample_blocks):
+    """Adjoint at full size.  F is linear in each psi_a and in the boosters of each edge, so a
+    central difference along a direction confined to one of them is exact up to rounding: the
+    psi gradients are checked entry by entry that way, the booster gradient along one random
+    direction per edge (forward passes on the GPU), and sampled booster blocks against the
+    oracle's gradient (only the shells that use them are visited)."""
+    b, bd = boosters_for(torch, two_j, dl, seed)
+    dims = [n for _, n in R.boundary_ranges(two_j)]
+    psis = workloads.boundary_vectors(psi_seed, dims)
+    pd = [torch.from_numpy(p).cuda() for p in psis]
+    A = lib.vertex_tensor(two_j, dl, 1.2, bd)
+    F = complex(lib.contract_boundary(A, pd).cpu().item())
+    g = load_golden(golden, required=False) if golden else None
+    if g is not None and len(g["rows"]) == dims[0]:
+        Fref = C.contract_boundary(g["A"], psis)
+        note(f"  F {F:.6e}, oracle {Fref:.6e}")
+        assert abs(F - Fref) <= TOL * abs(Fref)
+    gpsi, gb = lib.contract_boundary_adjoint(two_j, dl, bd, A, pd, 1.0)
+    gb = gb.cpu().numpy()
+    scale = max(abs(F), 1e-300)
+    for q in range(5):
+        gq = gpsi[q].cpu().numpy()
+        for n in range(dims[q]):
+            for delta in (1.0, 1.0j):
+                up = [p.clone() for p in pd]
+                dn = [p.clone() for p in pd]
+                up[q][n] += delta
+                dn[q][n] -= delta
+                fd = (complex(lib.contract_boundary(A, up).cpu().item())
+                      - complex(lib.contract_boundary(A, dn).cpu().item())) / 2
+                got = gq[n] * delta
+                assert abs(fd - got) <= 1e-12 * max(scale, abs(fd)), (q, n, fd, got)
+    shapes, offsets = R.booster_layout(two_j, dl)
+    n3 = (dl + 1) ** 3
+    rng = np.random.default_rng(7)
+    for e in range(2, 6):
+        lo, hi = offsets[(e - 2) * n3], offsets[(e - 1) * n3]
+        d = np.zeros_like(b)
+        d[lo:hi] = rng.standard_normal(hi - lo) * np.abs(b[lo:hi]).max()
+        dd = torch.from_numpy(d).cuda()
+        Fp = complex(lib.contract_boundary(lib.vertex_tensor(two_j, dl, 1.2, bd + dd), pd).cpu().item())
+        Fm = complex(lib.contract_boundary(lib.vertex_tensor(two_j, dl, 1.2, bd - dd), pd).cpu().item())
+        fd = (Fp - Fm) / 2
+        got = complex(np.dot(gb, d))
+        note(f"  edge {e}: directional derivative {got:.6e}, central difference {fd:.6e}")
+        assert abs(fd - got) <= 1e-10 * max(abs(fd), abs(Fp), abs(Fm))
+    ref = C.grad_boosters(two_j, dl, b, psis, only=sample_blocks)
+    for (e, t), blk in ref.items():
+        n = (e - 2) * n3 + t
+        got = gb[offsets[n]:offsets[n + 1]].reshape(blk.shape)
+        err = normwise(got, blk)
+        note(f"  booster block (e{e}, {t}) vs oracle gradient {err:.3e}")
+        assert err <= TOL
+
+
+def test_adjoint_j4_full_size(lib, torch):
+    cfg = workloads.CFG4
+    note("adjoint j=4 dl=8")
+    dl = cfg["dl"]
+    mid = ((dl // 2) * (dl + 1) + dl // 2) * (dl + 1) + dl // 2
+    _adjoint_full_size(lib, torch, cfg["two_j"], dl, cfg["booster_seed"], cfg["psi_seed"], "j4_dl8",
+                       [(2, 0), (5, mid)])
+
+
+def test_adjoint_large_spins(lib, torch):
+    tj, dl = workloads.cfg5_batch()[0]
+    note(f"adjoint large spins two_j={tj} dl={dl}")
+    _adjoint_full_size(lib, torch, tj, dl, workloads.batch_booster_seed(workloads.CFG5_SEED, 0),
+                       workloads.CFG5_SEED, None, [(3, 0)])

@@ -161,6 +161,18 @@ def test_vertex_against_brute_force_network(tj, dl):
     np.testing.assert_allclose(a, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
 
 
+def test_reduced_i1_rows_against_brute_force_network():
+    # A reduced set of boundary intertwiners i1 (Sec. 3.1): the rows asked for, in that order.
+    tj, dl = [3, 2, 4, 1, 2, 1, 4, 2, 2, 1], 1
+    ref = brute_force_vertex(tj, dl)
+    rows = [ref.shape[0] - 1, 0]
+    a = V.vertex_tensor(tj, dl, pack_named_boosters(tj, dl), i1_rows=rows)
+    assert a.shape == (2,) + ref.shape[1:]
+    np.testing.assert_allclose(a, ref[rows], rtol=0, atol=1e-13 * np.abs(ref).max())
+    with pytest.raises(ValueError):
+        V.vertex_tensor(tj, dl, pack_named_boosters(tj, dl), i1_rows=[ref.shape[0]])
+
+
 def test_fp64_tier_against_mpmath_tier():
     tj, dl = [2, 3, 2, 1, 3, 2, 3, 1, 1, 3], 1
     b = workloads.synthetic_boosters(5, R.block_shapes(tj, dl))
@@ -233,3 +245,20 @@ def test_gradients_against_finite_differences():
     fd = (C.contract_boundary(V.vertex_tensor(tj, dl, b + h * d), psis)
           - C.contract_boundary(V.vertex_tensor(tj, dl, b - h * d), psis)) / (2 * h)
     assert abs(fd - np.dot(gb, d)) <= 2e-8 * max(1.0, abs(fd))
+
+
+def test_restricted_booster_gradient_matches_full():
+    # Visiting only the shells that use the chosen blocks gives those blocks' full gradient.
+    tj, dl = [4, 1, 2, 3, 1, 3, 2, 4, 4, 1], 1
+    b = workloads.synthetic_boosters(6, R.block_shapes(tj, dl))
+    psis = workloads.boundary_vectors(6, [n for _, n in R.boundary_ranges(tj)])
+    full = C.grad_boosters(tj, dl, b, psis)
+    shapes, offsets = R.booster_layout(tj, dl)
+    n3 = (dl + 1) ** 3
+    only = [(2, 0), (3, 5), (5, 7)]
+    part = C.grad_boosters(tj, dl, b, psis, only=only)
+    assert sorted(part) == sorted(only)
+    for e, t in only:
+        n = (e - 2) * n3 + t
+        ref = full[offsets[n]:offsets[n + 1]].reshape(part[(e, t)].shape)
+        np.testing.assert_array_equal(part[(e, t)], ref)

@@ -85,3 +85,11 @@ def cfg3_batch():
 def cfg5_batch():
     """16 configurations, j in {5, 5.5, 6, 6.5, 7}, dl = 6 (seed 1005)."""
     return random_batch(1005, 16, [10, 11, 12, 13, 14], dl_fixed=6)
+
+
+CFG3_SEED, CFG5_SEED = 1003, 1005
+
+
+def batch_booster_seed(batch_seed, c):
+    """Seed of the synthetic boosters of configuration ``c`` of a seeded batch."""
+    return batch_seed + 1000 + c
