@@ -178,18 +178,24 @@ int ensure_fexp(eprl_ctx *c, int fact_max) {
 }
 
 // Device-side state of one configuration: tables built, metadata uploaded.
+// Workgroups per launch of the factorised path: enough for several rounds of resident
+// workgroups on 256 CUs, so that cost-balanced chunks finish together.  A batch uses the same
+// schedule per configuration, which keeps its tensors bitwise equal to those of plain calls.
+constexpr int kRingTargetWG = 8192;
+
 struct Prepared {
   Plan plan;
   double *tables = nullptr;
   int64_t *boff = nullptr;
   int *kr = nullptr;
+  int *sched = nullptr;  // chunk bounds of the factorised path, when asked for
   char *tail = nullptr;  // first free byte of the workspace after the above
 };
 
-// Plan, size the workspace (tables + metadata + `extra` bytes), upload metadata and build the
-// 6j tables.  `extra` is placed at `prep.tail`.
+// Plan, size the workspace (tables + metadata + `extra` bytes), upload metadata (and `sched`,
+// if given) and build the 6j tables.  `extra` is placed at `prep.tail`.
 int prepare(eprl_ctx *c, const int two_j[10], int dl, size_t extra, Prepared &prep,
-            bool ring_tables = false) {
+            bool ring_tables = false, const std::vector<int> *sched = nullptr) {
   int rc = make_plan(two_j, dl, prep.plan, c->err);
   if (rc) return rc;
   Plan &p = prep.plan;
@@ -200,18 +206,21 @@ int prepare(eprl_ctx *c, const int two_j[10], int dl, size_t extra, Prepared &pr
   const size_t tbytes = align_up((size_t)p.toff[5] * sizeof(double), 256);
   const size_t bbytes = align_up(p.boff.size() * sizeof(int64_t), 256);
   const size_t kbytes = align_up(p.kr.size() * sizeof(int), 256);
-  rc = ensure_workspace(c, tbytes + bbytes + kbytes + extra);
+  const size_t sbytes = sched ? align_up(sched->size() * sizeof(int), 256) : 0;
+  rc = ensure_workspace(c, tbytes + bbytes + kbytes + sbytes + extra);
   if (rc) return rc;
   prep.tables = reinterpret_cast<double *>(c->ws);
   prep.boff = reinterpret_cast<int64_t *>(c->ws + tbytes);
   prep.kr = reinterpret_cast<int *>(c->ws + tbytes + bbytes);
-  prep.tail = c->ws + tbytes + bbytes + kbytes;
+  prep.sched = sched ? reinterpret_cast<int *>(c->ws + tbytes + bbytes + kbytes) : nullptr;
+  prep.tail = c->ws + tbytes + bbytes + kbytes + sbytes;
   char *st;
-  rc = staging(c, bbytes + kbytes, &st);
+  rc = staging(c, bbytes + kbytes + sbytes, &st);
   if (rc) return rc;
   std::memcpy(st, p.boff.data(), p.boff.size() * sizeof(int64_t));
   std::memcpy(st + bbytes, p.kr.data(), p.kr.size() * sizeof(int));
-  rc = upload(c, prep.boff, bbytes + kbytes);
+  if (sched) std::memcpy(st + bbytes + kbytes, sched->data(), sched->size() * sizeof(int));
+  rc = upload(c, prep.boff, bbytes + kbytes + sbytes);
   if (rc) return rc;
   TableParams tp;
   std::memcpy(tp.two_j, p.two_j, sizeof(tp.two_j));
@@ -289,13 +298,11 @@ ReduceParams reduce_params(const Plan &p, const double *partial, int nchunk, dou
 // Factorised evaluation over all shells (one launch of the ring kernel, then the reduction).
 int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int accumulate,
               double *A, const Plan &probe) {
-  const int64_t ncore = (int64_t)probe.nd * probe.nd * probe.nd * probe.nd;
-  int nchunk = (int)std::min<int64_t>(ncore, std::max(1, 2048 / probe.i[0].n));
-  const int64_t chunk = (ncore + nchunk - 1) / nchunk;
-  nchunk = (int)((ncore + chunk - 1) / chunk);
+  std::vector<int> bounds;
+  const int nchunk = ring_schedule(probe, kRingTargetWG, bounds);
   const size_t pbytes = align_up((size_t)nchunk * probe.a_size * sizeof(double), 256);
   Prepared prep;
-  int rc = prepare(c, two_j, dl, pbytes, prep, true);
+  int rc = prepare(c, two_j, dl, pbytes, prep, true, &bounds);
   if (rc) return rc;
   const Plan &p = prep.plan;
   RingParams rp;
@@ -321,9 +328,7 @@ int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int acc
   rp.boff = prep.boff;
   rp.kr = prep.kr;
   rp.partial = reinterpret_cast<double *>(prep.tail);
-  rp.core_begin = 0;
-  rp.core_end = ncore;
-  rp.chunk = chunk;
+  rp.bounds = prep.sched;
   rp.nchunk = nchunk;
   {
     TimedLaunch tl(c, 4);
@@ -407,17 +412,16 @@ int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, co
 struct BatchEntry {
   Plan plan;
   bool ring = false;
-  size_t tables = 0, boff = 0, kr = 0, partial = 0;  // byte offsets in the batch workspace
+  size_t tables = 0, boff = 0, kr = 0, sched = 0, partial = 0;  // byte offsets in the workspace
   int nchunk = 0;
   int64_t chunk = 0;
+  std::vector<int> bounds;  // chunk bounds of the factorised path
 };
 
-int batch_chunks(const Plan &p, bool ring, int &nchunk, int64_t &chunk) {
+int batch_chunks(const Plan &p, bool ring, int &nchunk, int64_t &chunk, std::vector<int> &bounds) {
   if (ring) {
-    const int64_t ncore = (int64_t)p.nd * p.nd * p.nd * p.nd;
-    nchunk = (int)std::min<int64_t>(ncore, std::max(1, 2048 / p.i[0].n));
-    chunk = (ncore + nchunk - 1) / nchunk;
-    nchunk = (int)((ncore + chunk - 1) / chunk);
+    nchunk = ring_schedule(p, kRingTargetWG, bounds);
+    chunk = 0;
   } else {
     const int target_wg = p.D == 8 ? 4096 : 1024;
     nchunk = std::max(1, target_wg / p.i[0].n);
@@ -481,7 +485,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     b.ring = c->algo != EPRL_ALGO_SHELL && p.ring_KW != 0;
     if (c->algo == EPRL_ALGO_RING && !b.ring)
       return fail(c, EPRL_ERANGE, "the factorised path does not apply to every configuration");
-    batch_chunks(p, b.ring, b.nchunk, b.chunk);
+    batch_chunks(p, b.ring, b.nchunk, b.chunk, b.bounds);
     fact_max = std::max(fact_max, p.fact_max);
     if (b.ring) max_nd = std::max(max_nd, p.nd);
     b.tables = off;
@@ -490,6 +494,8 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     off += align_up(p.boff.size() * sizeof(int64_t), 256);
     b.kr = off;
     off += align_up(p.kr.size() * sizeof(int), 256);
+    b.sched = off;
+    off += align_up(b.bounds.size() * sizeof(int), 256);
     b.partial = off;
     off += align_up((size_t)b.nchunk * p.a_size * sizeof(double), 256);
   }
@@ -577,9 +583,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     rp.boff = reinterpret_cast<const int64_t *>(ws + ent[q].boff);
     rp.kr = reinterpret_cast<const int *>(ws + ent[q].kr);
     rp.partial = reinterpret_cast<double *>(ws + ent[q].partial);
-    rp.core_begin = 0;
-    rp.core_end = (int64_t)p.nd * p.nd * p.nd * p.nd;
-    rp.chunk = ent[q].chunk;
+    rp.bounds = reinterpret_cast<const int *>(ws + ent[q].sched);
     rp.nchunk = ent[q].nchunk;
   }
   // Compact staging of the metadata blocks: (workspace offset, bytes) in staging order.
@@ -600,6 +604,9 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
       const Plan &p = ent[q].plan;
       std::memcpy(st + so, p.boff.data(), p.boff.size() * sizeof(int64_t));
       std::memcpy(st + so + (ent[q].kr - ent[q].boff), p.kr.data(), p.kr.size() * sizeof(int));
+      if (!ent[q].bounds.empty())
+        std::memcpy(st + so + (ent[q].sched - ent[q].boff), ent[q].bounds.data(),
+                    ent[q].bounds.size() * sizeof(int));
       so += ent[q].partial - ent[q].boff;
     }
     std::memcpy(st + so, params.data(), params.size() * sizeof(RingParams));

@@ -97,7 +97,7 @@ struct RingParams {
   const int64_t *boff;
   const int *kr;
   double *partial;        // [nchunk][i1][i2][i3][i4][i5]
-  int64_t core_begin, core_end, chunk;
+  const int *bounds;      // [i1][nchunk + 1]: first core of each chunk of that i1
   int nchunk;
 };
 
@@ -120,6 +120,11 @@ hipError_t launch_sixj_batch(const int *args, int n, double *out, const uint16_t
 hipError_t launch_assemble(const VertexParams &vp, int D, hipStream_t s);
 hipError_t launch_reduce(const ReduceParams &rp, hipStream_t s);
 int ring_class(int DI, int DK, int KW);
+// Splits the cores of the factorised path, for each i1, into chunks of equal estimated cost
+// (x iterations plus the per-core set-up), about target_wg workgroups in all and at most
+// kRingMaxPartialBytes of partial sums; fills bounds ([i1][nchunk + 1]) and returns nchunk.
+constexpr size_t kRingMaxPartialBytes = size_t(256) << 20;
+int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds);
 int ring_row_blocks(int cls);
 size_t ring_smem_bytes(int cls, int nd);
 // Largest dl + 1 the ring kernels stage booster blocks for.

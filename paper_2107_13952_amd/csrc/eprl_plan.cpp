@@ -206,6 +206,75 @@ int make_plan(const int two_j[10], int dl, Plan &p, std::string &err) {
   return EPRL_OK;
 }
 
+int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds) {
+  const int nd = p.nd, nd3 = nd * nd * nd, d1 = p.i[0].n;
+  const int ncore = nd * nd3;
+  const int nrb = p.ring_cls >= 0 ? ring_row_blocks(p.ring_cls) : 1;
+  int nchunk = std::max(1, target_wg / (d1 * nrb));
+  nchunk = (int)std::min<int64_t>(nchunk, std::max<int64_t>(1, (int64_t)(kRingMaxPartialBytes / ((size_t)p.a_size * sizeof(double)))));
+  nchunk = std::min(nchunk, ncore);
+  const int *J = p.two_j;
+  const int xlo_g = p.X.lo2, xhi_g = p.X.lo2 + 2 * (p.X.n - 1);
+  std::vector<double> cost((size_t)d1 * ncore, 0.0);
+  for (int core = 0; core < ncore; ++core) {
+    const int o24 = core / nd3, o25 = (core / (nd * nd)) % nd, o34 = (core / nd) % nd, o35 = core % nd;
+    // Windows of k4 over l45 and of k3 over l23 (pairs with an empty range left out), as the
+    // kernel forms them.
+    int w4lo = 1 << 30, w4hi = -1, w3lo = 1 << 30, w3hi = -1;
+    for (int o = 0; o < nd; ++o) {
+      const int t5 = (o25 * nd + o35) * nd + o, t4 = (o * nd + o24) * nd + o34;
+      const int t2 = (o * nd + o24) * nd + o25, t3 = (o34 * nd + o35) * nd + o;
+      const int n5 = p.kr[(3 * nd3 + t5) * 2 + 1], n4 = p.kr[(2 * nd3 + t4) * 2 + 1];
+      const int n2 = p.kr[(0 * nd3 + t2) * 2 + 1], n3 = p.kr[(1 * nd3 + t3) * 2 + 1];
+      if (n5 > 0 && n4 > 0) {
+        const int lo = p.kr[(2 * nd3 + t4) * 2];
+        w4lo = std::min(w4lo, lo);
+        w4hi = std::max(w4hi, lo + 2 * (n4 - 1));
+      }
+      if (n2 > 0 && n3 > 0) {
+        const int lo = p.kr[(1 * nd3 + t3) * 2];
+        w3lo = std::min(w3lo, lo);
+        w3hi = std::max(w3hi, lo + 2 * (n3 - 1));
+      }
+    }
+    if (w4hi < 0 || w3hi < 0) {
+      for (int n1 = 0; n1 < d1; ++n1) cost[(size_t)n1 * ncore + core] = 0.1;
+      continue;
+    }
+    const int l24 = J[L24] + 2 * o24, l25 = J[L25] + 2 * o25, l35 = J[L35] + 2 * o35;
+    // x runs over (i1 l25 x) in steps of 2; both windows are non-empty exactly on
+    // max(w4lo - l35, l35 - w4hi) <= x <= l35 + w4hi and the same with (l24, w3).
+    const int lo_w = std::max(std::max(w4lo - l35, l35 - w4hi), std::max(w3lo - l24, l24 - w3hi));
+    const int hi_w = std::min(l35 + w4hi, l24 + w3hi);
+    for (int n1 = 0; n1 < d1; ++n1) {
+      const int i1 = p.i[0].lo2 + 2 * n1;
+      const int xlo = std::max(std::abs(i1 - l25), xlo_g), xhi = std::min(i1 + l25, xhi_g);
+      int lo = std::max(xlo, lo_w);
+      if ((lo - xlo) & 1) ++lo;
+      const int hi = std::min(xhi, hi_w);
+      const int nx = hi >= lo ? (hi - lo) / 2 + 1 : 0;
+      cost[(size_t)n1 * ncore + core] = 1.0 + nx;
+    }
+  }
+  bounds.assign((size_t)d1 * (nchunk + 1), 0);
+  for (int n1 = 0; n1 < d1; ++n1) {
+    const double *cs = cost.data() + (size_t)n1 * ncore;
+    double total = 0.0;
+    for (int k = 0; k < ncore; ++k) total += cs[k];
+    int *bd = bounds.data() + (size_t)n1 * (nchunk + 1);
+    double run = 0.0;
+    int k = 0;
+    for (int ch = 1; ch < nchunk; ++ch) {
+      const double target = total * ch / nchunk;
+      while (k < ncore && run + 0.5 * cs[k] < target) run += cs[k++];
+      bd[ch] = k;
+    }
+    bd[0] = 0;
+    bd[nchunk] = ncore;
+  }
+  return nchunk;
+}
+
 void count_terms(const Plan &p, int64_t &live, double &terms) {
   const int nd = p.nd, nd3 = nd * nd * nd;
   live = 0;

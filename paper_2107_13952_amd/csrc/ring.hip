@@ -32,6 +32,9 @@ namespace {
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int RT = 256;  // threads per workgroup
+#ifndef EPRL_RING_PIPELINE
+#define EPRL_RING_PIPELINE 0  // 1: load the next x's 6j columns during the current x
+#endif
 
 __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
@@ -42,6 +45,7 @@ __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 template <int DI, int DK, int KW>
 __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int rb, double *smem) {
   constexpr bool STAGE = DI == 8;  // booster blocks of a core staged in LDS (small tiles only)
+  constexpr bool PIPE = EPRL_RING_PIPELINE != 0;
   constexpr int GS = KW + 1;       // padded row stride of G and P
   constexpr int CC = DI * DI;      // columns (i3, i2)
   constexpr int CT = CC / 16;      // column tiles
@@ -74,8 +78,8 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
 #pragma unroll
   for (int cb = 0; cb < CT; ++cb) acc[cb] = d4v{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t c0 = rp.core_begin + chunk_index * rp.chunk;
-  const int64_t c1 = c0 + rp.chunk < rp.core_end ? c0 + rp.chunk : rp.core_end;
+  const int64_t c0 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index];
+  const int64_t c1 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index + 1];
   for (int64_t core = c0; core < c1; ++core) {
     const int o24 = (int)(core / (nd * nd * nd)), o25 = (int)((core / (nd * nd)) % nd);
     const int o34 = (int)((core / nd) % nd), o35 = (int)(core % nd);
@@ -120,121 +124,161 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
     if (w4hi < 0 || w3hi < 0) continue;  // uniform: no live shell in this core
     if (STAGE) {
       // Weighted booster blocks (2k+1) B of this core: e = 0 M5, 1 M4 (per l45), 2 M2, 3 M3
-      // (per l23); rows i, columns k relative to the lowest k of the block.
-      for (int idx = tid; idx < 4 * nd * DI * DK; idx += RT) {
-        const int e = idx / (nd * DI * DK), o = (idx / (DI * DK)) % nd;
-        const int i = (idx / DK) % DI, k = idx % DK;
+      // (per l23); rows i, columns k relative to the lowest k of the block; zero outside the
+      // block, pads included (reads below run past a row end and multiply by zero there).
+      for (int idx = tid; idx < 4 * nd * MBS; idx += RT) {
+        const int e = idx / (nd * MBS), o = (idx / MBS) % nd, r = idx % MBS;
+        const int i = r / DK, k = r % DK;
         const int lo = rng[(e == 0 ? 0 : e == 1 ? 2 : e == 2 ? 4 : 6) * nd + o];
         const int kn = rng[(e == 0 ? 1 : e == 1 ? 3 : e == 2 ? 5 : 7) * nd + o];
         const int ni = e == 0 ? d5 : e == 1 ? d4 : e == 2 ? d2 : d3;
         double v = 0.0;
         if (i < ni && k < kn) v = B[bo[e * nd + o] + (int64_t)i * kn + k] * (double)(lo + 2 * k + 1);
-        Mb[(e * nd + o) * MBS + i * DK + k] = v;
+        Mb[idx] = v;
       }
     }
     // x closes (i1 l25 x); the other triads restrict the k ranges at each x.
     const int xlo = imax(iabs(two_i1 - l25), rp.X_lo2), xhi = imin(two_i1 + l25, xhi_g);
     const int64_t u3base = (((int64_t)o24 * nd + o34) * nd + o35) * NX;
-    for (int x = xlo; x <= xhi; x += 2) {
+    // Active k4 and k3 windows at x (triads (k4 l35 x) and (k3 l24 x)); false if one is empty.
+    auto windows = [&](int x, int &a4, int &b4, int &a3, int &b3) {
+      a4 = imax(w4lo, iabs(l35 - x));
+      b4 = imin(w4hi, l35 + x);
+      a3 = imax(w3lo, iabs(l24 - x));
+      b3 = imin(w3hi, l24 + x);
+      return a4 <= b4 && a3 <= b3;
+    };
+    auto next_x = [&](int x) {  // first x >= x (same parity) with both windows non-empty
+      int a4, b4, a3, b3;
+      while (x <= xhi && !windows(x, a4, b4, a3, b3)) x += 2;
+      return x;
+    };
+    // Step-1 item u at x: its 6j column (pointers, stride, count c of active k5 or k2), the
+    // first active k (ka) and its index in the booster block (kk0).
+    auto item = [&](int u, int x, const double *&pa, const double *&pb, int &sb, int &c, int &ka,
+                    int &kk0) {
+      const int side = u / (nd * DK), o = (u / DK) % nd, ki = u % DK;
       const int xg = (x - rp.X_lo2) / 2;
-      const int a4 = imax(w4lo, iabs(l35 - x)), b4 = imin(w4hi, l35 + x);
-      const int a3 = imax(w3lo, iabs(l24 - x)), b3 = imin(w3hi, l24 + x);
-      if (a4 > b4 || a3 > b3) continue;  // uniform
-      const int a4l = (a4 - w4lo) / 2, b4l = (b4 - w4lo) / 2;
-      const int a3l = (a3 - w3lo) / 2, b3l = (b3 - w3lo) / 2;
-      const int x14lo = iabs(x - J[L14]), x14hi = x + J[L14];
-      const int x13lo = iabs(J[L13] - x), x13hi = J[L13] + x;
-      __syncthreads();  // previous x's readers of Gs / Hs / U3s are done
-      // U3 slice of this x, zero outside the active windows: loaded into registers here and
-      // stored to LDS after step 1, so that its loads and those of step 1 are in flight together.
-      constexpr int NU3 = (KW * KW + RT - 1) / RT;
-      double u3v[NU3];
+      int a4, b4, a3, b3;
+      windows(x, a4, b4, a3, b3);
+      if (side == 0) {
+        const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
+        const int k4 = lo4 + 2 * ki;
+        ka = imax(lo5, iabs(x - J[L14]));
+        const int kb = imin(lo5 + 2 * (n5 - 1), x + J[L14]);
+        c = (n5 > 0 && ki < n4 && k4 >= a4 && k4 <= b4 && kb >= ka) ? (kb - ka) / 2 + 1 : 0;
+        const int g0 = (ka - rp.K_lo2[3]) / 2, k4g = (k4 - rp.K_lo2[2]) / 2;
+        kk0 = c > 0 ? (ka - lo5) / 2 : 0;
+        pa = rp.U1 + (((int64_t)o25 * NX + xg) * d1 + n1) * nK5 + g0;
+        pb = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5 + g0) * nK4 + k4g;
+        sb = nK4;
+      } else {
+        const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
+        const int k3 = lo3 + 2 * ki;
+        ka = imax(lo2, iabs(J[L13] - x));
+        const int kb = imin(lo2 + 2 * (n2 - 1), J[L13] + x);
+        c = (n2 > 0 && ki < n3 && k3 >= a3 && k3 <= b3 && kb >= ka) ? (kb - ka) / 2 + 1 : 0;
+        const int g0 = (ka - rp.K_lo2[0]) / 2, k3g = (k3 - rp.K_lo2[1]) / 2;
+        kk0 = c > 0 ? (ka - lo2) / 2 : 0;
+        pa = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g) * nK2 + g0;
+        pb = rp.U5 + (((int64_t)o25 * NX + xg) * nK2 + g0) * d1 + n1;
+        sb = d1;
+      }
+    };
+    auto load_item = [&](int u, int x, double (&a)[DK], double (&b)[DK]) {
+      const double *pa, *pb;
+      int sb, c, ka, kk0;
+      item(u, x, pa, pb, sb, c, ka, kk0);
+#pragma unroll
+      for (int q = 0; q < DK; ++q) {
+        a[q] = q < c ? pa[q] : 0.0;
+        b[q] = q < c ? pb[(int64_t)q * sb] : 0.0;
+      }
+    };
+    // U3 slice at x, zero outside the active windows; this thread's entries.
+    constexpr int NU3 = (KW * KW + RT - 1) / RT;
+    auto load_u3 = [&](int x, double (&v)[NU3]) {
+      int a4, b4, a3, b3;
+      windows(x, a4, b4, a3, b3);
+      const int a4l = (a4 - w4lo) / 2, b4l = (b4 - w4lo) / 2, a3l = (a3 - w3lo) / 2, b3l = (b3 - w3lo) / 2;
+      const int xg = (x - rp.X_lo2) / 2;
 #pragma unroll
       for (int q = 0; q < NU3; ++q) {
         const int idx = tid + q * RT, k4l = idx / KW, k3l = idx % KW;
-        u3v[q] = 0.0;
+        v[q] = 0.0;
         if (idx < KW * KW && k4l >= a4l && k4l <= b4l && k3l >= a3l && k3l <= b3l) {
           const int k4g = (w4lo - rp.K_lo2[2]) / 2 + k4l, k3g = (w3lo - rp.K_lo2[1]) / 2 + k3l;
-          u3v[q] = rp.U3[((u3base + xg) * nK4 + k4g) * nK3 + k3g];
+          v[q] = rp.U3[((u3base + xg) * nK4 + k4g) * nK3 + k3g];
         }
       }
-      // Half chains, step 1: one item per (l45, k4) and per (l23, k3) reads its 6j column
-      // once for the whole workgroup:
-      //   T5(l45; i5, k4) = sum_k5 U1(k5) M5(i5, k5) U2(k5, k4)      (k5 active at this x)
-      //   T2(l23; k3, i2) = sum_k2 U4(k3, k2) M2(i2, k2) U5(k2)      (k2 active at this x)
-      for (int u = tid; u < 2 * nd * DK; u += RT) {
-        const int side = u / (nd * DK), o = (u / DK) % nd, ki = u % DK;
-        double a[DK], b[DK];
-        if (side == 0) {
-          const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
-          const int k4 = lo4 + 2 * ki;
-          const int ka = imax(lo5, x14lo), kb = imin(lo5 + 2 * (n5 - 1), x14hi);
-          const int c5 = (n5 > 0 && ki < n4 && k4 >= a4 && k4 <= b4 && kb >= ka) ? (kb - ka) / 2 + 1 : 0;
-          const int g0 = (ka - rp.K_lo2[3]) / 2, kk0 = (ka - lo5) / 2, k4g = (k4 - rp.K_lo2[2]) / 2;
-          const double *u1 = rp.U1 + (((int64_t)o25 * NX + xg) * d1 + n1) * nK5 + g0;
-          const double *u2 = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5 + g0) * nK4 + k4g;
+    };
+    // Step 1 for item u from its loaded column:
+    //   T5(l45; i5, k4) = sum_k5 U1(k5) M5(i5, k5) U2(k5, k4)      (k5 active at this x)
+    //   T2(l23; i2, k3) = sum_k2 U4(k3, k2) M2(i2, k2) U5(k2)      (k2 active at this x)
+    auto step1 = [&](int u, int x, double (&a)[DK], const double (&b)[DK]) {
+      const double *pa, *pb;
+      int sb, c, ka, kk0;
+      item(u, x, pa, pb, sb, c, ka, kk0);
+      const int side = u / (nd * DK), o = (u / DK) % nd, ki = u % DK;
 #pragma unroll
-          for (int q = 0; q < DK; ++q) {
-            a[q] = q < c5 ? u1[q] : 0.0;
-            b[q] = q < c5 ? u2[(int64_t)q * nK4] : 0.0;
-          }
+      for (int q = 0; q < DK; ++q) a[q] *= b[q];
+      const int e = side == 0 ? 0 : 2, ni = side == 0 ? d5 : d2, nrow = side == 0 ? IB : DI;
+      const int r0 = side == 0 ? rb * IB : 0;
+      // a[q] is zero for q >= c: the sums run over all DK terms without branches (staged rows
+      // read past their end into finite values; global rows clamp the index to the last one).
+      for (int il = 0; il < nrow; ++il) {
+        const int i = r0 + il;
+        double t = 0.0;
+        if (STAGE) {
+          const double *m = Mb + (e * nd + o) * MBS + i * DK + kk0;
 #pragma unroll
-          for (int q = 0; q < DK; ++q) a[q] *= b[q];
-          for (int i5l = 0; i5l < IB; ++i5l) {
-            const int i5 = rb * IB + i5l;
-            double t = 0.0;
-            if (c5 > 0 && i5 < d5) {
-              if (STAGE) {
-                const double *m5 = Mb + (0 * nd + o) * MBS + i5 * DK + kk0;
+          for (int q = 0; q < DK; ++q) t += a[q] * m[q];
+        } else if (c > 0 && i < ni) {
+          const int kn = rng[(e == 0 ? 1 : 5) * nd + o];
+          const double *m = B + bo[e * nd + o] + (int64_t)i * kn + kk0;
 #pragma unroll
-                for (int q = 0; q < DK; ++q)
-                  if (q < c5) t += a[q] * m5[q];
-              } else {
-                const double *m5 = B + bo[0 * nd + o] + (int64_t)i5 * n5 + kk0;
-#pragma unroll
-                for (int q = 0; q < DK; ++q)
-                  if (q < c5) t += a[q] * (m5[q] * (double)(ka + 2 * q + 1));
-              }
-            }
-            T5[o * T5S + i5l * DK + ki] = t;
-          }
-        } else {
-          const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
-          const int k3 = lo3 + 2 * ki;
-          const int ka = imax(lo2, x13lo), kb = imin(lo2 + 2 * (n2 - 1), x13hi);
-          const int c2 = (n2 > 0 && ki < n3 && k3 >= a3 && k3 <= b3 && kb >= ka) ? (kb - ka) / 2 + 1 : 0;
-          const int g0 = (ka - rp.K_lo2[0]) / 2, kk0 = (ka - lo2) / 2, k3g = (k3 - rp.K_lo2[1]) / 2;
-          const double *u4 = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g) * nK2 + g0;
-          const double *u5 = rp.U5 + (((int64_t)o25 * NX + xg) * nK2 + g0) * d1 + n1;
-#pragma unroll
-          for (int q = 0; q < DK; ++q) {
-            a[q] = q < c2 ? u4[q] : 0.0;
-            b[q] = q < c2 ? u5[(int64_t)q * d1] : 0.0;
-          }
-#pragma unroll
-          for (int q = 0; q < DK; ++q) a[q] *= b[q];
-          for (int i2 = 0; i2 < DI; ++i2) {
-            double t = 0.0;
-            if (c2 > 0 && i2 < d2) {
-              if (STAGE) {
-                const double *m2 = Mb + (2 * nd + o) * MBS + i2 * DK + kk0;
-#pragma unroll
-                for (int q = 0; q < DK; ++q)
-                  if (q < c2) t += a[q] * m2[q];
-              } else {
-                const double *m2 = B + bo[2 * nd + o] + (int64_t)i2 * n2 + kk0;
-#pragma unroll
-                for (int q = 0; q < DK; ++q)
-                  if (q < c2) t += a[q] * (m2[q] * (double)(ka + 2 * q + 1));
-              }
-            }
-            T2[o * T2S + i2 * DK + ki] = t;
-          }
+          for (int q = 0; q < DK; ++q) t += a[q] * (m[imin(q, c - 1)] * (double)(ka + 2 * q + 1));
         }
+        if (side == 0)
+          T5[o * T5S + il * DK + ki] = t;
+        else
+          T2[o * T2S + il * DK + ki] = t;
+      }
+    };
+    // With PIPE, the 6j columns of the first step-1 item of each thread and its U3 entries for
+    // the next x are loaded while step 2 and the two contractions of the current x run (more
+    // registers, fewer workgroups per CU); otherwise they are loaded at the start of step 1.
+    const bool first_item = tid < 2 * nd * DK;
+    double pa[DK], pb[DK], pu3[NU3];
+    int x = next_x(xlo);
+    if (PIPE && x <= xhi) {
+      load_u3(x, pu3);
+      if (first_item) load_item(tid, x, pa, pb);
+    }
+    while (x <= xhi) {
+      int a4, b4, a3, b3;
+      windows(x, a4, b4, a3, b3);
+      const int a4l = (a4 - w4lo) / 2, b4l = (b4 - w4lo) / 2;
+      const int a3l = (a3 - w3lo) / 2, b3l = (b3 - w3lo) / 2;
+      const int xn = next_x(x + 2);
+      __syncthreads();  // previous x's readers of Gs / Hs / U3s / T5 / T2 are done
+      if (!PIPE) {
+        load_u3(x, pu3);
+        if (first_item) load_item(tid, x, pa, pb);
+      }
+      if (first_item) step1(tid, x, pa, pb);
+      for (int u = tid + RT; u < 2 * nd * DK; u += RT) {
+        double a[DK], b[DK];
+        load_item(u, x, a, b);
+        step1(u, x, a, b);
       }
 #pragma unroll
       for (int q = 0; q < NU3; ++q)
-        if (tid + q * RT < KW * KW) U3s[((tid + q * RT) / KW) * U3S + (tid + q * RT) % KW] = u3v[q];
+        if (tid + q * RT < KW * KW) U3s[((tid + q * RT) / KW) * U3S + (tid + q * RT) % KW] = pu3[q];
+      if (PIPE && xn <= xhi) {
+        load_u3(xn, pu3);
+        if (first_item) load_item(tid, xn, pa, pb);
+      }
       __syncthreads();
       // Step 2: G(i5, i4, k4) = sum_l45 T5 M4 and H(k3, i3, i2) = sum_l23 M3 T2.
       for (int u = tid; u < IB * KW + KW * DI; u += RT) {
@@ -245,21 +289,26 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
           for (int q = 0; q < DI; ++q) g[q] = 0.0;
           if (k4l >= a4l && k4l <= b4l && i5 < d5) {
             const int k4 = w4lo + 2 * k4l;
+#pragma unroll 2
             for (int o = 0; o < nd; ++o) {
               const int n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
-              if (n5 == 0 || k4 < lo4 || k4 > lo4 + 2 * (n4 - 1)) continue;
-              const int k4i = (k4 - lo4) / 2;
-              const double t = T5[o * T5S + i5l * DK + k4i];
+              const int k4i = (k4 - lo4) >> 1;
+              const bool ok = n5 > 0 && k4 >= lo4 && k4i < n4;
               if (STAGE) {
-                const double *m4 = Mb + (1 * nd + o) * MBS + k4i;
+                // Branch-free: an l45 whose k4 range misses k4 contributes t = 0.
+                const int kc = ok ? k4i : 0;
+                const double t = ok ? T5[o * T5S + i5l * DK + kc] : 0.0;
+                const double *m4 = Mb + (1 * nd + o) * MBS + kc;
 #pragma unroll
                 for (int i4 = 0; i4 < DI; ++i4) g[i4] += t * m4[i4 * DK];
               } else {
+                if (!ok) continue;
+                const double t = T5[o * T5S + i5l * DK + k4i];
                 const double w4 = (double)(k4 + 1);
                 const double *m4 = B + bo[1 * nd + o] + k4i;
 #pragma unroll
                 for (int i4 = 0; i4 < DI; ++i4)
-                  if (i4 < d4) g[i4] += t * (m4[(int64_t)i4 * n4] * w4);
+                  g[i4] += t * (i4 < d4 ? m4[(int64_t)imin(i4, d4 - 1) * n4] * w4 : 0.0);
               }
             }
           }
@@ -272,21 +321,25 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
           for (int q = 0; q < DI; ++q) hq[q] = 0.0;
           if (k3l >= a3l && k3l <= b3l && i2 < d2) {
             const int k3 = w3lo + 2 * k3l;
+#pragma unroll 2
             for (int o = 0; o < nd; ++o) {
               const int n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
-              if (n2 == 0 || k3 < lo3 || k3 > lo3 + 2 * (n3 - 1)) continue;
-              const int k3i = (k3 - lo3) / 2;
-              const double t = T2[o * T2S + i2 * DK + k3i];
+              const int k3i = (k3 - lo3) >> 1;
+              const bool ok = n2 > 0 && k3 >= lo3 && k3i < n3;
               if (STAGE) {
-                const double *m3 = Mb + (3 * nd + o) * MBS + k3i;
+                const int kc = ok ? k3i : 0;
+                const double t = ok ? T2[o * T2S + i2 * DK + kc] : 0.0;
+                const double *m3 = Mb + (3 * nd + o) * MBS + kc;
 #pragma unroll
                 for (int i3 = 0; i3 < DI; ++i3) hq[i3] += t * m3[i3 * DK];
               } else {
+                if (!ok) continue;
+                const double t = T2[o * T2S + i2 * DK + k3i];
                 const double w3 = (double)(k3 + 1);
                 const double *m3 = B + bo[3 * nd + o] + k3i;
 #pragma unroll
                 for (int i3 = 0; i3 < DI; ++i3)
-                  if (i3 < d3) hq[i3] += t * (m3[(int64_t)i3 * n3] * w3);
+                  hq[i3] += t * (i3 < d3 ? m3[(int64_t)imin(i3, d3 - 1) * n3] * w3 : 0.0);
               }
             }
           }
@@ -328,6 +381,7 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
           }
         }
       }
+      x = xn;
     }
   }
   // Flush the partial A(i1, ...): row (i5, i4), column (i3, i2).
