@@ -251,12 +251,36 @@ __global__ __launch_bounds__(NT) void assemble_kernel(VertexParams vp) {
   }
 }
 
-// A = (accumulate ? A : 0) + prod_e sqrt(2 i_e + 1) * sum_chunks partial, in chunk order.
-__global__ void reduce_kernel(ReduceParams rp) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rp.a_size) return;
+// A = (accumulate ? A : 0) + prod_e sqrt(2 i_e + 1) * sum_chunks partial.  A workgroup of
+// RW wavefronts owns 64 consecutive entries; wavefront w sums the w-th of RW contiguous runs of
+// chunks in chunk order, then the RW run sums are added in run order: a fixed order for a given
+// chunk count, with enough loads in flight to stream the partials at HBM rate.
+constexpr int RW = 16;
+__global__ __launch_bounds__(64 * RW) void reduce_kernel(ReduceParams rp) {
+  __shared__ double run[RW][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+  const bool in = idx < rp.a_size;
+  const int c0 = (int)((int64_t)rp.nchunk * w / RW), c1 = (int)((int64_t)rp.nchunk * (w + 1) / RW);
   double s = 0.0;
-  for (int c = 0; c < rp.nchunk; ++c) s += rp.partial[(int64_t)c * rp.a_size + idx];
+  if (in) {
+    const double *p = rp.partial + idx;
+    int c = c0;
+    for (; c + 8 <= c1; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = p[(int64_t)(c + q) * rp.a_size];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; c < c1; ++c) s += p[(int64_t)c * rp.a_size];
+  }
+  run[w][lane] = s;
+  __syncthreads();
+  if (w != 0 || !in) return;
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < RW; ++q) t += run[q][lane];
   int64_t r = idx;
   double norm = 1.0;
   for (int e = 4; e >= 0; --e) {
@@ -264,7 +288,7 @@ __global__ void reduce_kernel(ReduceParams rp) {
     r /= rp.i_n[e];
     norm *= __builtin_sqrt((double)(rp.i_lo2[e] + 2 * n + 1));
   }
-  const double v = s * norm;
+  const double v = t * norm;
   rp.A[idx] = rp.accumulate ? rp.A[idx] + v : v;
 }
 
@@ -301,8 +325,8 @@ hipError_t launch_assemble(const VertexParams &vp, int D, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const ReduceParams &rp, hipStream_t s) {
-  const int64_t blocks = (rp.a_size + 255) / 256;
-  reduce_kernel<<<(unsigned)blocks, 256, 0, s>>>(rp);
+  const int64_t blocks = (rp.a_size + 63) / 64;
+  reduce_kernel<<<(unsigned)blocks, 64 * RW, 0, s>>>(rp);
   return hipGetLastError();
 }
 

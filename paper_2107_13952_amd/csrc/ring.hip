@@ -224,8 +224,8 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
       for (int q = 0; q < DK; ++q) a[q] *= b[q];
       const int e = side == 0 ? 0 : 2, ni = side == 0 ? d5 : d2, nrow = side == 0 ? IB : DI;
       const int r0 = side == 0 ? rb * IB : 0;
-      // a[q] is zero for q >= c: the sums run over all DK terms without branches (staged rows
-      // read past their end into finite values; global rows clamp the index to the last one).
+      // a[q] is zero for q >= c: staged sums run over all DK terms without branches (rows read
+      // past their end into finite values); global rows load only the c active entries.
       for (int il = 0; il < nrow; ++il) {
         const int i = r0 + il;
         double t = 0.0;
@@ -237,7 +237,8 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
           const int kn = rng[(e == 0 ? 1 : 5) * nd + o];
           const double *m = B + bo[e * nd + o] + (int64_t)i * kn + kk0;
 #pragma unroll
-          for (int q = 0; q < DK; ++q) t += a[q] * (m[imin(q, c - 1)] * (double)(ka + 2 * q + 1));
+          for (int q = 0; q < DK; ++q)
+            if (q < c) t += a[q] * (m[q] * (double)(ka + 2 * q + 1));
         }
         if (side == 0)
           T5[o * T5S + il * DK + ki] = t;
@@ -308,7 +309,7 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
                 const double *m4 = B + bo[1 * nd + o] + k4i;
 #pragma unroll
                 for (int i4 = 0; i4 < DI; ++i4)
-                  g[i4] += t * (i4 < d4 ? m4[(int64_t)imin(i4, d4 - 1) * n4] * w4 : 0.0);
+                  if (i4 < d4) g[i4] += t * (m4[(int64_t)i4 * n4] * w4);
               }
             }
           }
@@ -339,7 +340,7 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
                 const double *m3 = B + bo[3 * nd + o] + k3i;
 #pragma unroll
                 for (int i3 = 0; i3 < DI; ++i3)
-                  hq[i3] += t * (i3 < d3 ? m3[(int64_t)imin(i3, d3 - 1) * n3] * w3 : 0.0);
+                  if (i3 < d3) hq[i3] += t * (m3[(int64_t)i3 * n3] * w3);
               }
             }
           }
