@@ -32,6 +32,7 @@ namespace {
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int RT = 256;  // threads per workgroup
+constexpr size_t kLdsBytes = 160 * 1024 - 256;  // LDS of a CU, less room for static LDS
 #ifndef EPRL_RING_PIPELINE
 #define EPRL_RING_PIPELINE 0  // 1: load the next x's 6j columns during the current x
 #endif
@@ -42,9 +43,13 @@ __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
 // One work item: cores [chunk * rp.chunk, ...) of rp, boundary intertwiner i1 = n1, row
 // block rb (rows rb * 64 .. rb * 64 + 63 of A(i1; rows, cols)).
-template <int DI, int DK, int KW>
+// STG: booster blocks of a core staged in LDS: 2 all four (M5, M4, M2, M3), 1 the two read in
+// the second half-chain stage (M4, M3), 0 none (read from global memory).
+template <int DI, int DK, int KW, int STG>
 __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int rb, double *smem) {
-  constexpr bool STAGE = DI == 8;  // booster blocks of a core staged in LDS (small tiles only)
+  constexpr bool STAGE = STG == 2;   // M5, M2 in LDS (first stage)
+  constexpr bool STAGE2 = STG >= 1;  // M4, M3 in LDS (second stage)
+  constexpr int NBLK = STG == 2 ? 4 : 2 * STG;
   constexpr bool PIPE = EPRL_RING_PIPELINE != 0;
   constexpr int GS = KW + 1;       // padded row stride of G and P
   constexpr int CC = DI * DI;      // columns (i3, i2)
@@ -62,8 +67,10 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
   double *U3s = Hs + KW * HS;         // [KW][U3S] k4 x k3
   double *T5 = U3s + KW * U3S;        // [nd][T5S] per l45: sum_k5 U1 M5 U2 as [i5 of block][k4]
   double *T2 = T5 + nd * T5S;         // [nd][T2S] per l23: sum_k2 U4 M2 U5 as [i2][k3]
-  double *Mb = T2 + nd * T2S;         // [4][nd][MBS] weighted boosters M5, M4, M2, M3 as [i][k] (if STAGE)
-  int64_t *bo = reinterpret_cast<int64_t *>(Mb + (STAGE ? 4 * nd * MBS : 0));  // [4][nd]
+  double *Mb = T2 + nd * T2S;         // [NBLK][nd][MBS] weighted boosters as [i][k]
+  int64_t *bo = reinterpret_cast<int64_t *>(Mb + NBLK * nd * MBS);  // [4][nd]
+  // Offset in Mb of the block of edge slot e (0 M5, 1 M4, 2 M2, 3 M3) for the spin index o.
+  auto mb = [&](int e, int o) { return ((STG == 2 ? e : (e == 1 ? 0 : 1)) * nd + o) * MBS; };
   int *rng = reinterpret_cast<int *>(bo + 4 * nd);           // [8][nd] lo/n of k5, k4, k2, k3
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -122,12 +129,13 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
       }
     }
     if (w4hi < 0 || w3hi < 0) continue;  // uniform: no live shell in this core
-    if (STAGE) {
+    if (STG > 0) {
       // Weighted booster blocks (2k+1) B of this core: e = 0 M5, 1 M4 (per l45), 2 M2, 3 M3
       // (per l23); rows i, columns k relative to the lowest k of the block; zero outside the
       // block, pads included (reads below run past a row end and multiply by zero there).
-      for (int idx = tid; idx < 4 * nd * MBS; idx += RT) {
-        const int e = idx / (nd * MBS), o = (idx / MBS) % nd, r = idx % MBS;
+      for (int idx = tid; idx < NBLK * nd * MBS; idx += RT) {
+        const int blk = idx / (nd * MBS), o = (idx / MBS) % nd, r = idx % MBS;
+        const int e = STG == 2 ? blk : (blk == 0 ? 1 : 3);
         const int i = r / DK, k = r % DK;
         const int lo = rng[(e == 0 ? 0 : e == 1 ? 2 : e == 2 ? 4 : 6) * nd + o];
         const int kn = rng[(e == 0 ? 1 : e == 1 ? 3 : e == 2 ? 5 : 7) * nd + o];
@@ -230,7 +238,7 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
         const int i = r0 + il;
         double t = 0.0;
         if (STAGE) {
-          const double *m = Mb + (e * nd + o) * MBS + i * DK + kk0;
+          const double *m = Mb + mb(e, o) + i * DK + kk0;
 #pragma unroll
           for (int q = 0; q < DK; ++q) t += a[q] * m[q];
         } else if (c > 0 && i < ni) {
@@ -295,11 +303,11 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
               const int n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
               const int k4i = (k4 - lo4) >> 1;
               const bool ok = n5 > 0 && k4 >= lo4 && k4i < n4;
-              if (STAGE) {
+              if (STAGE2) {
                 // Branch-free: an l45 whose k4 range misses k4 contributes t = 0.
                 const int kc = ok ? k4i : 0;
                 const double t = ok ? T5[o * T5S + i5l * DK + kc] : 0.0;
-                const double *m4 = Mb + (1 * nd + o) * MBS + kc;
+                const double *m4 = Mb + mb(1, o) + kc;
 #pragma unroll
                 for (int i4 = 0; i4 < DI; ++i4) g[i4] += t * m4[i4 * DK];
               } else {
@@ -327,10 +335,10 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
               const int n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
               const int k3i = (k3 - lo3) >> 1;
               const bool ok = n2 > 0 && k3 >= lo3 && k3i < n3;
-              if (STAGE) {
+              if (STAGE2) {
                 const int kc = ok ? k3i : 0;
                 const double t = ok ? T2[o * T2S + i2 * DK + kc] : 0.0;
-                const double *m3 = Mb + (3 * nd + o) * MBS + kc;
+                const double *m3 = Mb + mb(3, o) + kc;
 #pragma unroll
                 for (int i3 = 0; i3 < DI; ++i3) hq[i3] += t * m3[i3 * DK];
               } else {
@@ -401,16 +409,16 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
   __syncthreads();  // the next item reuses the LDS
 }
 
-template <int DI, int DK, int KW>
+template <int DI, int DK, int KW, int STG>
 __global__ __launch_bounds__(RT) void ring_kernel(RingParams rp) {
   extern __shared__ double smem[];
-  ring_item<DI, DK, KW>(rp, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+  ring_item<DI, DK, KW, STG>(rp, blockIdx.x, blockIdx.y, blockIdx.z, smem);
 }
 
 // Persistent variant for batches: every workgroup walks a static, longest-first list of
 // (configuration, chunk, i1, row block) items with stride gridDim.x; no atomics, so the
 // assignment of items to workgroups (and every partial sum) is fixed.
-template <int DI, int DK, int KW>
+template <int DI, int DK, int KW, int STG>
 __global__ __launch_bounds__(RT) void ring_batch_kernel(const RingParams *cfgs, const int *items,
                                                         int nitems, int *next) {
   extern __shared__ double smem[];
@@ -425,7 +433,7 @@ __global__ __launch_bounds__(RT) void ring_batch_kernel(const RingParams *cfgs, 
     __syncthreads();
     if (it >= nitems) break;
     const int *p = items + 4 * it;
-    ring_item<DI, DK, KW>(cfgs[p[0]], p[1], p[2], p[3], smem);
+    ring_item<DI, DK, KW, STG>(cfgs[p[0]], p[1], p[2], p[3], smem);
   }
 }
 
@@ -434,47 +442,77 @@ __global__ void reset_counters(int *c, int n) {
   if (threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
-template <int DI, int DK, int KW>
+template <int DI, int DK, int KW, int STG>
 struct RingVariant {
   static constexpr size_t smem(int nd) {
-    const size_t stage = DI == 8 ? (size_t)4 * nd * (DI * DK + 2) : 0;
+    const size_t stage = (size_t)(STG == 2 ? 4 : 2 * STG) * nd * (DI * DK + 2);
     return sizeof(double) * ((size_t)(64 * (KW + 1) + KW * (DI * DI + 8) + KW * (KW == 32 ? KW + 8 : KW)) +
                              (size_t)nd * ((64 / DI + DI) * DK + 16) + stage) +
            sizeof(int64_t) * (size_t)(4 * nd) + sizeof(int) * (size_t)(8 * nd);
   }
-  static_assert(smem(kRingMaxNd) <= 160 * 1024, "ring tile class exceeds the LDS of a CU");
+  static constexpr bool fits(int nd) { return smem(nd) <= kLdsBytes; }
   static hipError_t init() {
-    const int bytes = (int)smem(kRingMaxNd);
-    hipError_t e = hipFuncSetAttribute((const void *)ring_kernel<DI, DK, KW>,
+    int nd = kRingMaxNd;
+    while (nd > 1 && !fits(nd)) --nd;
+    const int bytes = (int)smem(nd);
+    hipError_t e = hipFuncSetAttribute((const void *)ring_kernel<DI, DK, KW, STG>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)ring_batch_kernel<DI, DK, KW>,
+    return hipFuncSetAttribute((const void *)ring_batch_kernel<DI, DK, KW, STG>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   }
   static hipError_t launch(const RingParams &rp, hipStream_t s) {
     dim3 grid(rp.nchunk, rp.i_n[0], DI == 16 ? 4 : 1);
-    ring_kernel<DI, DK, KW><<<grid, RT, smem(rp.nd), s>>>(rp);
+    ring_kernel<DI, DK, KW, STG><<<grid, RT, smem(rp.nd), s>>>(rp);
     return hipGetLastError();
   }
   static hipError_t launch_batch(const RingParams *cfgs, const int *items, int nitems, int max_nd,
                                  int grid, int *next, hipStream_t s) {
-    ring_batch_kernel<DI, DK, KW><<<grid, RT, smem(max_nd), s>>>(cfgs, items, nitems, next);
+    ring_batch_kernel<DI, DK, KW, STG><<<grid, RT, smem(max_nd), s>>>(cfgs, items, nitems, next);
     return hipGetLastError();
   }
 };
 
-// Dispatch over the eight tile classes.
+static_assert(RingVariant<8, 16, 32, 2>::fits(kRingMaxNd) && RingVariant<8, 8, 32, 2>::fits(kRingMaxNd),
+              "8-wide tiles must fit with all booster blocks staged");
+static_assert(RingVariant<16, 16, 32, 0>::fits(kRingMaxNd), "16-wide tiles must fit unstaged");
+
+// Staging level for a 16-wide tile class at nd: the most booster blocks that fit in LDS.
+template <int DI, int DK, int KW, typename F>
+hipError_t pick_stage(int nd, F &&f) {
+  if (RingVariant<DI, DK, KW, 2>::fits(nd)) return f(RingVariant<DI, DK, KW, 2>());
+  if (RingVariant<DI, DK, KW, 1>::fits(nd)) return f(RingVariant<DI, DK, KW, 1>());
+  return f(RingVariant<DI, DK, KW, 0>());
+}
+
+// Dispatch over the eight tile classes (and, for 16-wide tiles, the staging level at nd).
+// 8-wide tiles always stage all four blocks; nd = 0 visits every variant (attribute set-up).
 template <typename F>
-hipError_t dispatch(int cls, F &&f) {
+hipError_t dispatch(int cls, int nd, F &&f) {
+  if (nd == 0 && cls >= 4) {
+    hipError_t e = hipSuccess;
+    auto all = [&](auto v0, auto v1, auto v2) {
+      if (e == hipSuccess) e = f(v0);
+      if (e == hipSuccess) e = f(v1);
+      if (e == hipSuccess) e = f(v2);
+      return e;
+    };
+    switch (cls) {
+      case 4: return all(RingVariant<16, 8, 16, 0>(), RingVariant<16, 8, 16, 1>(), RingVariant<16, 8, 16, 2>());
+      case 5: return all(RingVariant<16, 8, 32, 0>(), RingVariant<16, 8, 32, 1>(), RingVariant<16, 8, 32, 2>());
+      case 6: return all(RingVariant<16, 16, 16, 0>(), RingVariant<16, 16, 16, 1>(), RingVariant<16, 16, 16, 2>());
+      default: return all(RingVariant<16, 16, 32, 0>(), RingVariant<16, 16, 32, 1>(), RingVariant<16, 16, 32, 2>());
+    }
+  }
   switch (cls) {
-    case 0: return f(RingVariant<8, 8, 16>());
-    case 1: return f(RingVariant<8, 8, 32>());
-    case 2: return f(RingVariant<8, 16, 16>());
-    case 3: return f(RingVariant<8, 16, 32>());
-    case 4: return f(RingVariant<16, 8, 16>());
-    case 5: return f(RingVariant<16, 8, 32>());
-    case 6: return f(RingVariant<16, 16, 16>());
-    case 7: return f(RingVariant<16, 16, 32>());
+    case 0: return f(RingVariant<8, 8, 16, 2>());
+    case 1: return f(RingVariant<8, 8, 32, 2>());
+    case 2: return f(RingVariant<8, 16, 16, 2>());
+    case 3: return f(RingVariant<8, 16, 32, 2>());
+    case 4: return pick_stage<16, 8, 16>(nd, f);
+    case 5: return pick_stage<16, 8, 32>(nd, f);
+    case 6: return pick_stage<16, 16, 16>(nd, f);
+    case 7: return pick_stage<16, 16, 32>(nd, f);
     default: return hipErrorInvalidValue;
   }
 }
@@ -490,7 +528,7 @@ int ring_row_blocks(int cls) { return cls >= 4 ? 4 : 1; }
 
 size_t ring_smem_bytes(int cls, int nd) {
   size_t out = 0;
-  dispatch(cls, [&](auto v) {
+  dispatch(cls, nd, [&](auto v) {
     out = decltype(v)::smem(nd);
     return hipSuccess;
   });
@@ -501,20 +539,20 @@ size_t ring_smem_bytes(int cls, int nd) {
 // per process before any launch (not a stream operation, so never inside a graph capture).
 hipError_t ring_init_attributes() {
   for (int cls = 0; cls < 8; ++cls) {
-    hipError_t e = dispatch(cls, [](auto v) { return decltype(v)::init(); });
+    hipError_t e = dispatch(cls, 0, [](auto v) { return decltype(v)::init(); });
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
 hipError_t launch_ring(const RingParams &rp, int cls, hipStream_t s) {
-  return dispatch(cls, [&](auto v) { return decltype(v)::launch(rp, s); });
+  return dispatch(cls, rp.nd, [&](auto v) { return decltype(v)::launch(rp, s); });
 }
 
 hipError_t launch_ring_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems, int cls,
                              int max_nd, int grid, int *next, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  return dispatch(cls, [&](auto v) {
+  return dispatch(cls, max_nd, [&](auto v) {
     return decltype(v)::launch_batch(cfgs_dev, items_dev, nitems, max_nd, grid, next, s);
   });
 }
