@@ -93,8 +93,9 @@ def main():
     ap.add_argument("--no-paper-order", action="store_true", help="skip timing the per-shell order")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the vertex tensor on a single "
-              "MI355X (see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the vertex tensor runs on a single MI355X "
+              "(several GPUs would split the shell sum by ranges of cores); use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
