@@ -17,8 +17,10 @@ Prints one JSON line:
   batched      cfg3-shaped batch (64 seeded configurations): batched call vs per-config calls
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -56,6 +58,37 @@ def cpu_baseline(two_j, dl, boosters_np, nshell_sample):
                       f"{terms:.3g} terms in {dt:.1f} s, one thread"}
 
 
+def measured_traffic():
+    """HBM bytes per ring_kernel launch from the committed counter summary, when it was taken on
+    the current kernel source (same sha256 prefix); otherwise None."""
+    path = os.path.join(ROOT, "profiles", "ring_kernel_j3_dl8_counters.md")
+    src = os.path.join(ROOT, "paper_2107_13952_amd", "csrc", "ring.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m = re.search(r"kernel source sha256 ([0-9a-f]{16})", text)
+    t = re.search(r"traffic bytes per launch: ([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != digest:
+        return None
+    return float(t.group(1))
+
+
+def counter_workload(lib, torch, two_j, dl, b):
+    """The dominant kernel three times and a plain 256 MiB device copy three times (the copy
+    calibrates what FETCH_SIZE and WRITE_SIZE read for a known number of bytes)."""
+    for _ in range(3):
+        lib.vertex_tensor(two_j, dl, 1.2, b)
+    torch.cuda.synchronize()
+    x = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("counter workload done", flush=True)
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -91,6 +124,8 @@ def main():
     ap.add_argument("--cpu-shells", type=int, default=3000, help="oracle sample size (0 = skip)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper-order", action="store_true", help="skip timing the per-shell order")
+    ap.add_argument("--counter-workload", action="store_true",
+                    help="run the dominant kernel and a calibration copy for rocprofv3 --pmc, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the vertex tensor runs on a single MI355X "
@@ -114,6 +149,9 @@ def main():
     work = lib.count_work(two_j, dl)
     progress(f"workload two_j={two_j} dl={dl}: {live} live shells, {terms:.3g} terms")
     out = torch.empty(dims, dtype=torch.float64, device=dev)
+    if args.counter_workload:
+        counter_workload(lib, torch, two_j, dl, b)
+        return
 
     lib.set_algorithm("auto")
     ms, ring_ms, kernels = time_steps(lib, torch, two_j, dl, b, out, args.steps, args.warmup, "ring")
@@ -140,11 +178,14 @@ def main():
                    "two_j": two_j, "dl": dl, "live_shells": live, "terms": terms,
                    "algorithm": "factorised shell sum (ring), FP64 matrix-core contractions"},
         "roofline": {"bound": "mfma", "achieved": useful, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": useful / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": useful / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(),
                      "kernel": "ring_kernel", "avg_ms": ring_ms,
                      "alg_flops_per_launch": work["ring_useful_flops"],
                      "alg_flops_per_term": work["ring_useful_flops"] / terms,
-                     "mfma_executed_tflops": executed},
+                     "mfma_executed_tflops": executed,
+                     "per_shell_order_flops_over_time_tflops":
+                         work["shell_flops"] / (ring_ms * 1e-3) / 1e12},
         "kernels_ms": kernels,
     }
     if not args.no_paper_order:
