@@ -33,9 +33,6 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int RT = 256;  // threads per workgroup
 constexpr size_t kLdsBytes = 160 * 1024 - 256;  // LDS of a CU, less room for static LDS
-#ifndef EPRL_RING_PIPELINE
-#define EPRL_RING_PIPELINE 0  // 1: load the next x's 6j columns during the current x
-#endif
 
 __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
@@ -50,7 +47,6 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
   constexpr bool STAGE = STG == 2;   // M5, M2 in LDS (first stage)
   constexpr bool STAGE2 = STG >= 1;  // M4, M3 in LDS (second stage)
   constexpr int NBLK = STG == 2 ? 4 : 2 * STG;
-  constexpr bool PIPE = EPRL_RING_PIPELINE != 0;
   constexpr int GS = KW + 1;       // padded row stride of G and P
   constexpr int CC = DI * DI;      // columns (i3, i2)
   constexpr int CT = CC / 16;      // column tiles
@@ -80,6 +76,10 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
   const int NX = rp.NX, nK2 = rp.K_n[0], nK3 = rp.K_n[1], nK4 = rp.K_n[2], nK5 = rp.K_n[3];
   const int xhi_g = rp.X_lo2 + 2 * (NX - 1);
   const double *B = rp.B;
+
+  // This thread's first step-1 item (u = tid): side 0 (T5, per l45) or 1 (T2, per l23).
+  const bool first_item = tid < 2 * nd * DK;
+  const int f_side = tid / (nd * DK), f_o = (tid / DK) % nd, f_ki = tid % DK;
 
   d4v acc[CT];
 #pragma unroll
@@ -223,11 +223,10 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
     // Step 1 for item u from its loaded column:
     //   T5(l45; i5, k4) = sum_k5 U1(k5) M5(i5, k5) U2(k5, k4)      (k5 active at this x)
     //   T2(l23; i2, k3) = sum_k2 U4(k3, k2) M2(i2, k2) U5(k2)      (k2 active at this x)
-    auto step1 = [&](int u, int x, double (&a)[DK], const double (&b)[DK]) {
-      const double *pa, *pb;
-      int sb, c, ka, kk0;
-      item(u, x, pa, pb, sb, c, ka, kk0);
-      const int side = u / (nd * DK), o = (u / DK) % nd, ki = u % DK;
+    // The rows of step 1 for item (side, o, ki) from its loaded column: a[q], b[q] hold the q-th
+    // active k5 (k2), zero for q >= c; ka is the first active k, kk0 its index in the block.
+    auto step1_rows = [&](int side, int o, int ki, int c, int ka, int kk0, double (&a)[DK],
+                          const double (&b)[DK]) {
 #pragma unroll
       for (int q = 0; q < DK; ++q) a[q] *= b[q];
       const int e = side == 0 ? 0 : 2, ni = side == 0 ? d5 : d2, nrow = side == 0 ? IB : DI;
@@ -254,16 +253,42 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
           T2[o * T2S + il * DK + ki] = t;
       }
     };
-    // With PIPE, the 6j columns of the first step-1 item of each thread and its U3 entries for
-    // the next x are loaded while step 2 and the two contractions of the current x run (more
-    // registers, fewer workgroups per CU); otherwise they are loaded at the start of step 1.
-    const bool first_item = tid < 2 * nd * DK;
-    double pa[DK], pb[DK], pu3[NU3];
-    int x = next_x(xlo);
-    if (PIPE && x <= xhi) {
-      load_u3(x, pu3);
-      if (first_item) load_item(tid, x, pa, pb);
+    auto step1 = [&](int u, int x, double (&a)[DK], const double (&b)[DK]) {
+      const double *pa, *pb;
+      int sb, c, ka, kk0;
+      item(u, x, pa, pb, sb, c, ka, kk0);
+      step1_rows(u / (nd * DK), (u / DK) % nd, u % DK, c, ka, kk0, a, b);
+    };
+    // This thread's first step-1 item u = tid (the same for every core): its geometry for this
+    // core is set up once here; per x only the active k range and one pointer offset change.
+    int f_lo = 0, f_n = 0, f_kc = 0, f_sb = 0;
+    bool f_kv = false;
+    const double *f_pa = rp.U1, *f_pb = rp.U1;
+    int64_t f_pax = 0, f_pbx = 0;
+    if (first_item) {
+      const int sh = f_side == 0 ? 0 : 4;
+      f_lo = rng[(sh + 0) * nd + f_o];
+      f_n = rng[(sh + 1) * nd + f_o];
+      f_kc = rng[(sh + 2) * nd + f_o] + 2 * f_ki;
+      f_kv = f_n > 0 && f_ki < rng[(sh + 3) * nd + f_o];
+      if (f_side == 0) {
+        const int g0 = (f_lo - rp.K_lo2[3]) / 2, kg = (f_kc - rp.K_lo2[2]) / 2;
+        f_pa = rp.U1 + ((int64_t)o25 * NX * d1 + n1) * nK5 + g0;                     // U1[o25][x][i1][k5]
+        f_pax = (int64_t)d1 * nK5;
+        f_pb = rp.U2 + (((int64_t)o35 * nd + f_o) * NX * nK5 + g0) * nK4 + kg;        // U2[o35][o45][x][k5][k4]
+        f_pbx = (int64_t)nK5 * nK4;
+        f_sb = nK4;
+      } else {
+        const int g0 = (f_lo - rp.K_lo2[0]) / 2, kg = (f_kc - rp.K_lo2[1]) / 2;
+        f_pa = rp.U4 + (((int64_t)f_o * nd + o24) * NX * nK3 + kg) * nK2 + g0;        // U4[o23][o24][x][k3][k2]
+        f_pax = (int64_t)nK3 * nK2;
+        f_pb = rp.U5 + ((int64_t)o25 * NX * nK2 + g0) * d1 + n1;                      // U5[o25][x][k2][i1]
+        f_pbx = (int64_t)nK2 * d1;
+        f_sb = d1;
+      }
     }
+    double pu3[NU3];
+    int x = next_x(xlo);
     while (x <= xhi) {
       int a4, b4, a3, b3;
       windows(x, a4, b4, a3, b3);
@@ -271,11 +296,25 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
       const int a3l = (a3 - w3lo) / 2, b3l = (b3 - w3lo) / 2;
       const int xn = next_x(x + 2);
       __syncthreads();  // previous x's readers of Gs / Hs / U3s / T5 / T2 are done
-      if (!PIPE) {
-        load_u3(x, pu3);
-        if (first_item) load_item(tid, x, pa, pb);
+      load_u3(x, pu3);
+      if (first_item) {
+        // Active k5 (k2) values at x: the triad (k5 j14 x) (or (j13 k2 x)) and the block range;
+        // the item is empty unless its k4 (k3) lies in the active window.
+        const int jq = f_side == 0 ? J[L14] : J[L13];
+        const int ka = imax(f_lo, iabs(x - jq)), kb = imin(f_lo + 2 * (f_n - 1), x + jq);
+        const bool inw = f_side == 0 ? (f_kc >= a4 && f_kc <= b4) : (f_kc >= a3 && f_kc <= b3);
+        const bool ok = f_kv && inw && kb >= ka;
+        const int c = ok ? (kb - ka) / 2 + 1 : 0, kk0 = ok ? (ka - f_lo) / 2 : 0;
+        const int xg = (x - rp.X_lo2) / 2;
+        const double *pa = f_pa + xg * f_pax + kk0, *pb = f_pb + xg * f_pbx + (int64_t)kk0 * f_sb;
+        double a[DK], b[DK];
+#pragma unroll
+        for (int q = 0; q < DK; ++q) {
+          a[q] = q < c ? pa[q] : 0.0;
+          b[q] = q < c ? pb[(int64_t)q * f_sb] : 0.0;
+        }
+        step1_rows(f_side, f_o, f_ki, c, f_lo + 2 * kk0, kk0, a, b);
       }
-      if (first_item) step1(tid, x, pa, pb);
       for (int u = tid + RT; u < 2 * nd * DK; u += RT) {
         double a[DK], b[DK];
         load_item(u, x, a, b);
@@ -284,10 +323,6 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
 #pragma unroll
       for (int q = 0; q < NU3; ++q)
         if (tid + q * RT < KW * KW) U3s[((tid + q * RT) / KW) * U3S + (tid + q * RT) % KW] = pu3[q];
-      if (PIPE && xn <= xhi) {
-        load_u3(xn, pu3);
-        if (first_item) load_item(tid, xn, pa, pb);
-      }
       __syncthreads();
       // Step 2: G(i5, i4, k4) = sum_l45 T5 M4 and H(k3, i3, i2) = sum_l23 M3 T2.
       for (int u = tid; u < IB * KW + KW * DI; u += RT) {
@@ -409,8 +444,15 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
   __syncthreads();  // the next item reuses the LDS
 }
 
+// Wavefronts per SIMD that the LDS of a tile class allows at the usual nd (<= 11): the register
+// budget is capped to match, so registers never limit occupancy below LDS.
+template <int DI, int DK, int KW>
+constexpr int ring_waves() {
+  return (DI == 8 && DK == 8 && KW == 16) ? 3 : (DI == 8 && (DK == 8 || KW == 16)) ? 2 : 1;
+}
+
 template <int DI, int DK, int KW, int STG>
-__global__ __launch_bounds__(RT) void ring_kernel(RingParams rp) {
+__global__ __launch_bounds__(RT, (ring_waves<DI, DK, KW>())) void ring_kernel(RingParams rp) {
   extern __shared__ double smem[];
   ring_item<DI, DK, KW, STG>(rp, blockIdx.x, blockIdx.y, blockIdx.z, smem);
 }
@@ -419,7 +461,7 @@ __global__ __launch_bounds__(RT) void ring_kernel(RingParams rp) {
 // (configuration, chunk, i1, row block) items with stride gridDim.x; no atomics, so the
 // assignment of items to workgroups (and every partial sum) is fixed.
 template <int DI, int DK, int KW, int STG>
-__global__ __launch_bounds__(RT) void ring_batch_kernel(const RingParams *cfgs, const int *items,
+__global__ __launch_bounds__(RT, (ring_waves<DI, DK, KW>())) void ring_batch_kernel(const RingParams *cfgs, const int *items,
                                                         int nitems, int *next) {
   extern __shared__ double smem[];
   __shared__ int it_s;
