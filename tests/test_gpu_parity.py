@@ -153,6 +153,48 @@ def test_vertex_tensor_small(lib, torch, algo, two_j, dl, seed):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("dl", [0, 2])
+def test_all_spins_zero(lib, torch, algo, dl):
+    """Degenerate vertex: all ten spins 0, one intertwiner per node (a 1x1x1x1x1 tensor)."""
+    b, bd = boosters_for(torch, [0] * 10, dl, 17 + dl)
+    note(f"all spins zero [{algo}] dl={dl}")
+    a = vertex_or_skip(lib, algo, [0] * 10, dl, 1.2, bd).cpu().numpy()
+    ref = V.vertex_tensor([0] * 10, dl, b)
+    assert a.shape == (1, 1, 1, 1, 1)
+    assert normwise(a, ref) <= TOL
+
+
+def test_largest_shell_grid(lib, torch):
+    """16 values per virtual spin (dl = 15), the largest grid of the factorised path: both orders
+    agree on the full tensor and the per-shell order matches the oracle on the last 4000 shells
+    (the largest virtual spins); dl = 16 runs in the per-shell order only."""
+    two_j, dl = [1] * 10, 15
+    b, bd = boosters_for(torch, two_j, dl, 18)
+    n = (dl + 1) ** 6
+    note("largest shell grid: dl=15 factorised vs per-shell")
+    ring = lib.vertex_tensor(two_j, dl, 1.2, bd).cpu().numpy()
+    lib.set_algorithm("shell")
+    try:
+        shell = lib.vertex_tensor(two_j, dl, 1.2, bd).cpu().numpy()
+        part = lib.vertex_tensor_range(two_j, dl, 1.2, bd, n - 4000, n).cpu().numpy()
+    finally:
+        lib.set_algorithm("auto")
+    assert normwise(ring, shell) <= 1e-12
+    ref = V.vertex_tensor(two_j, dl, b, shells=R.all_shells(dl)[n - 4000:])
+    assert normwise(part, ref) <= TOL
+    note("dl=16: per-shell order only")
+    b16, bd16 = boosters_for(torch, two_j, 16, 19)
+    a16 = lib.vertex_tensor(two_j, 16, 1.2, bd16)
+    assert torch.isfinite(a16).all()
+    lib.set_algorithm("ring")
+    try:
+        with pytest.raises(lib.EprlError) as exc:
+            lib.vertex_tensor(two_j, 16, 1.2, bd16)
+        assert exc.value.code == -4
+    finally:
+        lib.set_algorithm("auto")
+
+
 def test_bf_limit_identity_boosters(lib, torch, algo):
     two_j = [2, 3, 2, 1, 3, 2, 3, 1, 1, 3]
     shapes, offsets = R.booster_layout(two_j, 0)

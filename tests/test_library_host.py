@@ -76,3 +76,12 @@ def test_invalid_inputs_rejected():
         lib.layout([2] * 10, -1)
     with pytest.raises(lib.EprlError):
         lib.layout([20, 2, 2, 2, 2, 2, 2, 2, 2, 2], 0)      # polygon inequality violated
+
+
+def test_factorised_path_limits():
+    # 16 values per virtual spin (dl = 15) is the largest grid of the factorised order; beyond it
+    # and for intertwiner dimensions above 16 only the per-shell order applies.
+    lib = _lib()
+    assert lib.count_work([1] * 10, 15)["ring_class"] >= 0
+    assert lib.count_work([1] * 10, 16)["ring_class"] == -1
+    assert lib.count_work([6] * 10, 8)["ring_class"] == 0
