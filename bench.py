@@ -14,7 +14,9 @@ Prints one JSON line:
                index ranges need) against the FP64 matrix peak, with its average duration
                measured by HIP events on the library's stream
   cpu_baseline the CPU oracle timed on a bounded sample of the same workload
-  batched      cfg3-shaped batch (64 seeded configurations): batched call vs per-config calls
+  batched      64 seeded irregular configurations (dl 3..10): batched call vs per-config calls
+  differentiation  j=4, dl=8 forward, contraction and adjoint, adjoint vs central differences
+  large_batch  16 seeded large-spin configurations (dl 6): batched vs per-config calls
 """
 import argparse
 import hashlib
@@ -89,6 +91,76 @@ def counter_workload(lib, torch, two_j, dl, b):
     print("counter workload done", flush=True)
 
 
+def timed(torch, fn, reps):
+    """Average wall time of fn() over reps calls after one untimed call, synchronised."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def block_shapes(lib, two_j, dl):
+    """(rows, cols) of every packed booster block, from the library's layout."""
+    dims, _, offs = lib.layout(two_j, dl)
+    n3 = (dl + 1) ** 3
+    return [(dims[e + 1], int((offs[e * n3 + t + 1] - offs[e * n3 + t]) // dims[e + 1]))
+            for e in range(4) for t in range(n3)]
+
+
+def differentiation(lib, torch, dev):
+    """j=4, dl=8 vertex contracted with five seeded boundary vectors: forward, contraction and
+    adjoint times, and the adjoint's booster gradient against central differences along one random
+    direction per edge (F is linear in each edge's boosters, so the difference is exact up to
+    rounding)."""
+    cfg = workloads.CFG4
+    two_j, dl = cfg["two_j"], cfg["dl"]
+    b_np = workloads.synthetic_boosters(cfg["booster_seed"], block_shapes(lib, two_j, dl))
+    b = torch.from_numpy(b_np).to(dev)
+    dims, _, offsets = lib.layout(two_j, dl)
+    psis = [torch.from_numpy(p).to(dev) for p in workloads.boundary_vectors(cfg["psi_seed"], dims)]
+    A = lib.vertex_tensor(two_j, dl, 1.2, b)
+    t_fwd = timed(torch, lambda: lib.vertex_tensor(two_j, dl, 1.2, b, out=A), 3)
+    t_con = timed(torch, lambda: lib.contract_boundary(A, psis), 10)
+    t_adj = timed(torch, lambda: lib.contract_boundary_adjoint(two_j, dl, b, A, psis, 1.0), 2)
+    _, gb = lib.contract_boundary_adjoint(two_j, dl, b, A, psis, 1.0)
+    gb = gb.cpu().numpy()
+    n3 = (dl + 1) ** 3
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for e in range(4):
+        lo, hi = offsets[e * n3], offsets[(e + 1) * n3]
+        d = np.zeros_like(b_np)
+        d[lo:hi] = rng.standard_normal(hi - lo) * np.abs(b_np[lo:hi]).max()
+        dd = torch.from_numpy(d).to(dev)
+        fp = complex(lib.contract_boundary(lib.vertex_tensor(two_j, dl, 1.2, b + dd), psis).cpu().item())
+        fm = complex(lib.contract_boundary(lib.vertex_tensor(two_j, dl, 1.2, b - dd), psis).cpu().item())
+        fd = (fp - fm) / 2
+        worst = max(worst, abs(fd - complex(np.dot(gb, d))) / max(abs(fd), abs(fp), abs(fm)))
+    terms = lib.count_terms(two_j, dl)[1]
+    return {"workload": "equilateral j=4 (two_j=8), dl=8, five seeded unit complex boundary vectors",
+            "forward_ms": t_fwd * 1e3, "forward_terms_per_s": terms / t_fwd,
+            "contract_us": t_con * 1e6, "adjoint_ms": t_adj * 1e3,
+            "adjoint_vs_central_difference_max_rel_err": worst}
+
+
+def large_batch(lib, torch, dev):
+    """16 seeded configurations with spins 5..7 and dl = 6: batched graph vs per-configuration calls."""
+    configs = workloads.cfg5_batch()
+    bl = [torch.from_numpy(workloads.synthetic_boosters(
+        workloads.batch_booster_seed(workloads.CFG5_SEED, c), block_shapes(lib, tj, d))).to(dev)
+        for c, (tj, d) in enumerate(configs)]
+    terms = sum(lib.count_terms(tj, d)[1] for tj, d in configs)
+    outs = lib.vertex_tensor_batched(configs, 1.2, bl)
+    t_b = timed(torch, lambda: lib.vertex_tensor_batched(configs, 1.2, bl, outs), 1)
+    t_p = timed(torch, lambda: [lib.vertex_tensor(tj, d, 1.2, bb, out=a)
+                                for (tj, d), bb, a in zip(configs, bl, outs)], 1)
+    return {"workload": "16 seeded configurations, j in 5..7, dl = 6, intertwiner dims 11..14",
+            "terms": terms, "batched_terms_per_s": terms / t_b, "plain_terms_per_s": terms / t_p}
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -124,6 +196,8 @@ def main():
     ap.add_argument("--cpu-shells", type=int, default=3000, help="oracle sample size (0 = skip)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper-order", action="store_true", help="skip timing the per-shell order")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the j=4 forward/adjoint block")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-spin batch block")
     ap.add_argument("--counter-workload", action="store_true",
                     help="run the dominant kernel and a calibration copy for rocprofv3 --pmc, then exit")
     args = ap.parse_args()
@@ -225,6 +299,12 @@ def main():
         result["batched"] = {"workload": "64 seeded configurations, j in 1/2..6, dl in 3..10",
                              "terms": bterms, "batched_terms_per_s": bterms / t_batched,
                              "plain_terms_per_s": bterms / t_plain}
+    if not args.no_adjoint:
+        progress("differentiation: j=4 dl=8 forward, contraction, adjoint")
+        result["differentiation"] = differentiation(lib, torch, dev)
+    if not args.no_large:
+        progress("large-spin batch: 16 configurations")
+        result["large_batch"] = large_batch(lib, torch, dev)
     if args.cpu_shells > 0:
         progress(f"cpu baseline: oracle on {args.cpu_shells} shells")
         result["cpu_baseline"] = cpu_baseline(two_j, dl, b_np, args.cpu_shells)

@@ -330,6 +330,27 @@ def test_batched_full_size(lib, torch):
         assert torch.equal(outs[c], lib.vertex_tensor(tj, dl, 1.2, bds[c]))
 
 
+def test_batched_large_spins(lib, torch):
+    """The 16-configuration large-spin batch (intertwiner dimensions 11..14, dl = 6) in one batched
+    call: stored oracle rows of two configurations and bitwise equality with plain calls."""
+    configs = workloads.cfg5_batch()
+    bds = [boosters_for(torch, tj, dl, workloads.batch_booster_seed(workloads.CFG5_SEED, c))[1]
+           for c, (tj, dl) in enumerate(configs)]
+    note("batched large spins")
+    outs = lib.vertex_tensor_batched(configs, 1.2, bds)
+    for name in ("b5_c00_rows", "b5_c03_rows"):
+        c = int(name[4:6])
+        g = load_golden(name, required=False)
+        if g is None:
+            continue
+        err = normwise(outs[c].cpu().numpy()[g["rows"]], g["A"])
+        note(f"  {name} normwise error {err:.3e}")
+        assert err <= TOL
+    for c in (0, 3, 15):
+        tj, dl = configs[c]
+        assert torch.equal(outs[c], lib.vertex_tensor(tj, dl, 1.2, bds[c]))
+
+
 def test_batched_equals_plain(lib, torch):
     configs = workloads.cfg3_batch()[:6]
     configs = [(tj, min(dl, 2)) for tj, dl in configs]
