@@ -73,8 +73,9 @@ int eprl_set_stream(eprl_ctx *ctx, void *hip_stream);
  *  EPRL_ALGO_RING   the same sum regrouped by linearity: for each x of eq. (15j) and each
  *                   (l24, l25, l34, l35) the l45 and l23 sums are taken inside the two halves
  *                   of the closed chain of 6j and booster matrices, then contracted over k4 and
- *                   k3 with FP64 matrix-core tiles.  Needs every i and k range <= 8 and is used
- *                   for full-range calls only;
+ *                   k3 with FP64 matrix-core tiles.  Needs every i and k range <= 16 and at
+ *                   most 16 values per virtual spin (dl <= 15); used for full-range calls
+ *                   only (EPRL_ERANGE when forced where it does not apply);
  *  EPRL_ALGO_AUTO   (default) RING where it applies, SHELL otherwise. */
 #define EPRL_ALGO_AUTO 0
 #define EPRL_ALGO_SHELL 1
@@ -105,10 +106,10 @@ int eprl_count_terms(const int two_j[10], int dl, int64_t *live_shells, double *
  *            the configuration falls back to the per-shell order. */
 int eprl_count_work(const int two_j[10], int dl, double out[5]);
 
-/* The vertex tensor of eq. (vertex-ampl), computed by the framed algorithm of Sec. 3.1:
- * 6j tables (step 4), then per shell the {15j} tensor W (6(i)), the booster sub-matrices
- * (6(ii)), their contraction with W over k5, k4, k3, k2 (6(iii)) and the accumulation
- * (6(iv)); finally A *= prod_e sqrt(2 i_e + 1).
+/* The vertex tensor of eq. (vertex-ampl): the sum of the framed algorithm of Sec. 3.1 (6j
+ * tables (step 4); per shell the {15j} tensor W (6(i)) contracted with the booster
+ * sub-matrices (6(ii)) over k5, k4, k3, k2 (6(iii)) and accumulated (6(iv)); finally
+ * A *= prod_e sqrt(2 i_e + 1)), evaluated in the order set by eprl_set_algorithm.
  *   boosters  device, booster_offsets[last] doubles in the packed layout
  *   A         device, prod(dims_i) doubles, overwritten
  *   gamma     the Barbero-Immirzi parameter the boosters were computed with; it enters A only
@@ -125,8 +126,10 @@ int eprl_vertex_tensor_range(eprl_ctx *ctx, const int two_j[10], int dl, double 
                              int accumulate, double *A);
 
 /* n independent vertex tensors (configuration c: two_j[10 c .. 10 c + 9], dl[c],
- * boosters[c], A[c]) computed by one persistent launch; the host arrays of pointers hold
- * device pointers.  Results equal n calls of eprl_vertex_tensor. */
+ * boosters[c], A[c]); the host arrays of pointers hold device pointers.  The 6j tables, one
+ * persistent launch per tile class over a longest-first work queue of all configurations and
+ * the reductions are captured into a HIP graph, replayed while the configurations, pointers
+ * and algorithm are unchanged.  Results are bitwise equal to n calls of eprl_vertex_tensor. */
 int eprl_vertex_tensor_batched(eprl_ctx *ctx, int n, const int *two_j, const int *dl,
                                double gamma, const double *const *boosters, double *const *A);
 
@@ -161,8 +164,8 @@ int eprl_shell_fifteenj(eprl_ctx *ctx, const int two_j[10], int dl, int64_t shel
 
 /* Per-kernel timing with HIP events recorded on the context's stream around each launch.
  * kernel ids: 0 = 6j table builder, 1 = per-shell vertex assembly, 2 = shell-sum reduction,
- * 3 = adjoint shell kernel, 4 = factorised (ring) vertex assembly.  eprl_timing_enable(ctx, 1) starts recording (clearing earlier
- * records), 0 stops.  eprl_timing_read synchronises the stream and returns the summed
+ * 3 = adjoint shell kernel, 4 = factorised (ring) vertex assembly.  eprl_timing_enable(ctx, 1)
+ * starts recording (clearing earlier records), 0 stops.  eprl_timing_read synchronises the stream and returns the summed
  * duration in milliseconds and the number of launches recorded for `kernel`. */
 int eprl_timing_enable(eprl_ctx *ctx, int enable);
 int eprl_timing_read(eprl_ctx *ctx, int kernel, double *total_ms, int64_t *launches);

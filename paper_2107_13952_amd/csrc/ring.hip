@@ -20,9 +20,11 @@
 // has DI^2 rows (i5, i4) and DI^2 columns (i3, i2).  One workgroup (4 wavefronts) owns a
 // block of 64 rows (all of them for DI = 8, a quarter for DI = 16) of A(i1, ...) for a chunk
 // of cores and keeps it in MFMA accumulators; wavefront w owns row tile w and every column
-// tile.  Per x: the two half chains on VALU (loads of one l45 / l23 issued together), the U3
-// slice in LDS, then two 16x16x4 FP64 MFMA contractions.  Partial slices are reduced in a
-// fixed order by the shell-path reduction kernel.
+// tile.  Per x: the two half chains on VALU in two stages through LDS (step 1: T5 per (l45, k4)
+// and T2 per (l23, k3), each 6j column read once per workgroup; step 2: G and H over l45 and
+// l23 with the core's weighted booster blocks staged in LDS as far as they fit), the U3 slice in
+// LDS, then two 16x16x4 FP64 MFMA contractions.  The cores of each i1 are split into chunks of
+// equal estimated cost; partial slices are reduced in a fixed order by the reduction kernel.
 #include "eprl_internal.hpp"
 
 namespace eprl {
@@ -38,8 +40,8 @@ __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
-// One work item: cores [chunk * rp.chunk, ...) of rp, boundary intertwiner i1 = n1, row
-// block rb (rows rb * 64 .. rb * 64 + 63 of A(i1; rows, cols)).
+// One work item: cores [bounds[i1][chunk], bounds[i1][chunk + 1]) of rp, boundary intertwiner
+// i1 = n1, row block rb (rows rb * 64 .. rb * 64 + 63 of A(i1; rows, cols)).
 // STG: booster blocks of a core staged in LDS: 2 all four (M5, M4, M2, M3), 1 the two read in
 // the second half-chain stage (M4, M3), 0 none (read from global memory).
 template <int DI, int DK, int KW, int STG>
@@ -457,9 +459,8 @@ __global__ __launch_bounds__(RT, (ring_waves<DI, DK, KW>())) void ring_kernel(Ri
   ring_item<DI, DK, KW, STG>(rp, blockIdx.x, blockIdx.y, blockIdx.z, smem);
 }
 
-// Persistent variant for batches: every workgroup walks a static, longest-first list of
-// (configuration, chunk, i1, row block) items with stride gridDim.x; no atomics, so the
-// assignment of items to workgroups (and every partial sum) is fixed.
+// Persistent variant for batches: workgroups take (configuration, chunk, i1, row block) items
+// of a longest-first list from a counter (see below).
 template <int DI, int DK, int KW, int STG>
 __global__ __launch_bounds__(RT, (ring_waves<DI, DK, KW>())) void ring_batch_kernel(const RingParams *cfgs, const int *items,
                                                         int nitems, int *next) {
