@@ -60,9 +60,11 @@ def cpu_baseline(two_j, dl, boosters_np, nshell_sample):
                       f"{terms:.3g} terms in {dt:.1f} s, one thread"}
 
 
-def measured_traffic():
+def measured_traffic(split=None):
     """HBM bytes per ring_kernel launch from the committed counter summary, when it was taken on
-    the current kernel source (same sha256 prefix); otherwise None."""
+    the current kernel source (same sha256 prefix) with the work split timed here (default:
+    8192 workgroups, all booster blocks staged); otherwise None."""
+    target, stg = (8192, 2) if split is None else (split["target_workgroups"], split["staging_level"])
     path = os.path.join(ROOT, "profiles", "ring_kernel_j3_dl8_counters.md")
     src = os.path.join(ROOT, "paper_2107_13952_amd", "csrc", "ring.hip")
     try:
@@ -71,15 +73,18 @@ def measured_traffic():
     except OSError:
         return None
     m = re.search(r"kernel source sha256 ([0-9a-f]{16})", text)
-    t = re.search(r"traffic bytes per launch: ([0-9.eE+]+)", text)
+    t = re.search(r"traffic bytes per launch, split %d %d: ([0-9.eE+]+)" % (target, stg), text)
     if not m or not t or m.group(1) != digest:
         return None
     return float(t.group(1))
 
 
-def counter_workload(lib, torch, two_j, dl, b):
-    """The dominant kernel three times and a plain 256 MiB device copy three times (the copy
-    calibrates what FETCH_SIZE and WRITE_SIZE read for a known number of bytes)."""
+def counter_workload(lib, torch, two_j, dl, b, split):
+    """The dominant kernel three times (with the given work split) and a plain 256 MiB device copy
+    three times (the copy calibrates what FETCH_SIZE and WRITE_SIZE read for a known number of
+    bytes)."""
+    cls = lib.count_work(two_j, dl)["ring_class"]
+    lib.set_tuning(cls, split[0], split[1])
     for _ in range(3):
         lib.vertex_tensor(two_j, dl, 1.2, b)
     torch.cuda.synchronize()
@@ -196,10 +201,14 @@ def main():
     ap.add_argument("--cpu-shells", type=int, default=3000, help="oracle sample size (0 = skip)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper-order", action="store_true", help="skip timing the per-shell order")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default work split instead of the autotuned one")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the j=4 forward/adjoint block")
     ap.add_argument("--no-large", action="store_true", help="skip the large-spin batch block")
     ap.add_argument("--counter-workload", action="store_true",
                     help="run the dominant kernel and a calibration copy for rocprofv3 --pmc, then exit")
+    ap.add_argument("--counter-split", type=int, nargs=2, default=[8192, 2],
+                    metavar=("WORKGROUPS", "STAGING"), help="work split for --counter-workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the vertex tensor runs on a single MI355X "
@@ -224,10 +233,14 @@ def main():
     progress(f"workload two_j={two_j} dl={dl}: {live} live shells, {terms:.3g} terms")
     out = torch.empty(dims, dtype=torch.float64, device=dev)
     if args.counter_workload:
-        counter_workload(lib, torch, two_j, dl, b)
+        counter_workload(lib, torch, two_j, dl, b, args.counter_split)
         return
 
     lib.set_algorithm("auto")
+    tuned = None
+    if not args.no_autotune:
+        tuned = lib.autotune(two_j, dl, b, out)
+        progress(f"autotuned: {tuned}")
     ms, ring_ms, kernels = time_steps(lib, torch, two_j, dl, b, out, args.steps, args.warmup, "ring")
     progress(f"factorised order: {ms:.3f} ms/step, ring kernel {ring_ms:.3f} ms")
     useful = work["ring_useful_flops"] / (ring_ms * 1e-3) / 1e12
@@ -250,10 +263,11 @@ def main():
         "config": {"workload": "plain EPRL vertex tensor, equilateral j=3 (two_j=6), dl=8, "
                                "gamma=1.2, intertwiners 0..6 (7^5 FP64 tensor)",
                    "two_j": two_j, "dl": dl, "live_shells": live, "terms": terms,
-                   "algorithm": "factorised shell sum (ring), FP64 matrix-core contractions"},
+                   "algorithm": "factorised shell sum (ring), FP64 matrix-core contractions",
+                   "work_split": tuned or "default"},
         "roofline": {"bound": "mfma", "achieved": useful, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": useful / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(),
+                     "traffic": measured_traffic(tuned),
                      "kernel": "ring_kernel", "avg_ms": ring_ms,
                      "alg_flops_per_launch": work["ring_useful_flops"],
                      "alg_flops_per_term": work["ring_useful_flops"] / terms,

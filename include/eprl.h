@@ -82,6 +82,26 @@ int eprl_set_stream(eprl_ctx *ctx, void *hip_stream);
 #define EPRL_ALGO_RING 2
 int eprl_set_algorithm(eprl_ctx *ctx, int algo);
 
+/* Work split of the factorised order per tile class (the class is out[4] of eprl_count_work):
+ * the shell sum is cut into chunks of cores of equal estimated cost, about target_workgroups
+ * workgroups per launch (0: the default, 8192), and staging_level picks how many booster blocks
+ * of a core are held in LDS (2: all four, 1: the two of the second stage, 0: none, -1: the
+ * most that fits; a level that does not fit falls back to the next lower one).  The paper
+ * adapts the split of its loops to the machine in the same spirit (Sec. 3.1,
+ * "Parallelization").  The split changes the order of the floating-point sums (results agree
+ * to rounding) but every call with the same setting is bitwise repeatable, and plain and
+ * batched calls use the same setting.  EPRL_EINVAL for values out of range. */
+int eprl_set_tuning(eprl_ctx *ctx, int tile_class, int target_workgroups, int staging_level);
+
+/* Autotuner: times the vertex tensor of this configuration (boosters device, A device scratch
+ * of prod(dims_i) doubles, overwritten) in the factorised order for target workgroups
+ * 2048, 4096, 8192, 16384 and every staging level that fits, keeps the fastest setting for
+ * the configuration's tile class on this context (as eprl_set_tuning would) and writes
+ * out[0] = tile class, out[1] = target workgroups, out[2] = staging level.  Synchronises the
+ * context's stream.  EPRL_ERANGE when the factorised order does not apply. */
+int eprl_autotune(eprl_ctx *ctx, const int two_j[10], int dl, const double *boosters, double *A,
+                  int out[3]);
+
 /* Host-only (no GPU use).  Ranges of the vertex tensor (eq. (vertex-ampl)) and the packed
  * booster layout described above.
  *   dims_i[5]        out: dim(i1) .. dim(i5)

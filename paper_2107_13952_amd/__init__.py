@@ -40,6 +40,8 @@ _SIGS = {
     "eprl_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "eprl_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "eprl_set_algorithm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "eprl_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "eprl_autotune": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, _dp, _dp, _i32p]),
     "eprl_layout": (ctypes.c_int, [_i32p, ctypes.c_int, _i32p, _i32p, _i64p]),
     "eprl_count_terms": (ctypes.c_int, [_i32p, ctypes.c_int, _i64p, ctypes.POINTER(ctypes.c_double)]),
     "eprl_count_work": (ctypes.c_int, [_i32p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
@@ -299,6 +301,28 @@ def set_algorithm(name, device="cuda"):
     """Select how vertex tensors are evaluated: "auto" (default), "shell" or "ring"."""
     ctx = _ctx(device)
     ctx.check(_lib.eprl_set_algorithm(ctx.handle, ALGORITHMS[name]))
+
+
+def set_tuning(tile_class, target_workgroups=0, staging_level=-1, device="cuda"):
+    """Work split of the factorised order for one tile class (0 / -1 restore the defaults)."""
+    ctx = _ctx(device)
+    ctx.check(_lib.eprl_set_tuning(ctx.handle, int(tile_class), int(target_workgroups),
+                                   int(staging_level)))
+
+
+def autotune(two_j, dl, boosters, out=None):
+    """Time the factorised order on this configuration over workgroup targets and staging
+    levels and keep the fastest for its tile class; returns the chosen setting."""
+    torch = _torch()
+    dims, _, _ = layout(two_j, dl)
+    if out is None:
+        out = torch.empty(dims, dtype=torch.float64, device=boosters.device)
+    res = (ctypes.c_int * 3)()
+    ctx = _ctx(boosters.device)
+    ctx.check(_lib.eprl_autotune(ctx.bind(), _ints(two_j, 10), int(dl),
+                                 _check_dev(boosters, torch.float64, "boosters"),
+                                 _check_dev(out, torch.float64, "A"), res))
+    return {"tile_class": res[0], "target_workgroups": res[1], "staging_level": res[2]}
 
 
 def timing_enable(enable=True, device="cuda"):

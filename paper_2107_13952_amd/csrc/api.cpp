@@ -37,6 +37,11 @@ struct eprl_ctx {
   };
   std::vector<Rec> recs;
   bool capturing = false;
+  // Schedule per tile class of the factorised path (set by eprl_autotune or eprl_set_tuning):
+  // workgroup target of the cost schedule (0: default) and booster staging level (-1: the
+  // most that fits).
+  int tune_wg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int tune_stg[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   // Batched path: a dedicated workspace and the instantiated graph of the last batch.
   struct Batch {
     std::vector<int64_t> key;
@@ -299,7 +304,8 @@ ReduceParams reduce_params(const Plan &p, const double *partial, int nchunk, dou
 int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int accumulate,
               double *A, const Plan &probe) {
   std::vector<int> bounds;
-  const int nchunk = ring_schedule(probe, kRingTargetWG, bounds);
+  const int cls = probe.ring_cls;
+  const int nchunk = ring_schedule(probe, c->tune_wg[cls] > 0 ? c->tune_wg[cls] : kRingTargetWG, bounds);
   const size_t pbytes = align_up((size_t)nchunk * probe.a_size * sizeof(double), 256);
   Prepared prep;
   int rc = prepare(c, two_j, dl, pbytes, prep, true, &bounds);
@@ -332,7 +338,7 @@ int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int acc
   rp.nchunk = nchunk;
   {
     TimedLaunch tl(c, 4);
-    HIP_TRY(c, launch_ring(rp, p.ring_cls, c->stream));
+    HIP_TRY(c, launch_ring(rp, p.ring_cls, c->tune_stg[p.ring_cls], c->stream));
   }
   ReduceParams red = reduce_params(p, rp.partial, nchunk, A, accumulate);
   {
@@ -418,9 +424,10 @@ struct BatchEntry {
   std::vector<int> bounds;  // chunk bounds of the factorised path
 };
 
-int batch_chunks(const Plan &p, bool ring, int &nchunk, int64_t &chunk, std::vector<int> &bounds) {
+int batch_chunks(const Plan &p, bool ring, int target_wg, int &nchunk, int64_t &chunk,
+                 std::vector<int> &bounds) {
   if (ring) {
-    nchunk = ring_schedule(p, kRingTargetWG, bounds);
+    nchunk = ring_schedule(p, target_wg > 0 ? target_wg : kRingTargetWG, bounds);
     chunk = 0;
   } else {
     const int target_wg = p.D == 8 ? 4096 : 1024;
@@ -456,6 +463,10 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   std::vector<int64_t> key;
   key.push_back(n);
   key.push_back(c->algo);
+  for (int q = 0; q < 8; ++q) {
+    key.push_back(c->tune_wg[q]);
+    key.push_back(c->tune_stg[q]);
+  }
   for (int q = 0; q < n; ++q) {
     for (int t = 0; t < 10; ++t) key.push_back(two_j[10 * q + t]);
     key.push_back(dl[q]);
@@ -485,7 +496,8 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     b.ring = c->algo != EPRL_ALGO_SHELL && p.ring_KW != 0;
     if (c->algo == EPRL_ALGO_RING && !b.ring)
       return fail(c, EPRL_ERANGE, "the factorised path does not apply to every configuration");
-    batch_chunks(p, b.ring, b.nchunk, b.chunk, b.bounds);
+    batch_chunks(p, b.ring, p.ring_cls >= 0 ? c->tune_wg[p.ring_cls] : 0, b.nchunk, b.chunk,
+                 b.bounds);
     fact_max = std::max(fact_max, p.fact_max);
     if (b.ring) max_nd = std::max(max_nd, p.nd);
     b.tables = off;
@@ -652,12 +664,12 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     const int nit = cls_begin[cls + 1] - cls_begin[cls];
     if (nit == 0) continue;
     // Enough workgroups to fill the chip at the occupancy the tile class allows.
-    const size_t shm = ring_smem_bytes(cls, max_nd);
+    const size_t shm = ring_smem_bytes(cls, max_nd, c->tune_stg[cls]);
     const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(shm, 1))));
     const int grid = (int)std::min<int>(nit, ncu * per_cu);
     e = launch_ring_batch(reinterpret_cast<const RingParams *>(ws + params_off),
                           reinterpret_cast<const int *>(ws + items_off) + 4 * cls_begin[cls], nit,
-                          cls, max_nd, grid, counters + cls, c->stream);
+                          cls, max_nd, c->tune_stg[cls], grid, counters + cls, c->stream);
   }
   for (int q = 0; q < n && e == hipSuccess; ++q) {
     if (ent[q].ring) continue;
@@ -747,6 +759,80 @@ int eprl_set_algorithm(eprl_ctx *c, int algo) {
   if (algo != EPRL_ALGO_AUTO && algo != EPRL_ALGO_SHELL && algo != EPRL_ALGO_RING)
     return fail(c, EPRL_EINVAL, "unknown algorithm");
   c->algo = algo;
+  return EPRL_OK;
+}
+
+int eprl_set_tuning(eprl_ctx *c, int tile_class, int target_workgroups, int staging_level) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (tile_class < 0 || tile_class > 7) return fail(c, EPRL_EINVAL, "tile class outside 0..7");
+  if (target_workgroups != 0 && (target_workgroups < 64 || target_workgroups > (1 << 20)))
+    return fail(c, EPRL_EINVAL, "workgroup target must be 0 or in 64..2^20");
+  if (staging_level < -1 || staging_level > 2)
+    return fail(c, EPRL_EINVAL, "staging level must be -1, 0, 1 or 2");
+  c->tune_wg[tile_class] = target_workgroups;
+  c->tune_stg[tile_class] = staging_level;
+  return EPRL_OK;
+}
+
+int eprl_autotune(eprl_ctx *c, const int two_j[10], int dl, const double *B, double *A,
+                  int out[3]) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!B || !A || !out) return fail(c, EPRL_EINVAL, "null pointer");
+  Plan p;
+  int rc = make_plan(two_j, dl, p, c->err);
+  if (rc) return rc;
+  if (p.ring_cls < 0) return fail(c, EPRL_ERANGE, "no tile class of the factorised order applies");
+  const int cls = p.ring_cls;
+  int levels[3];
+  const int nl = ring_stage_levels(cls, p.nd, levels);
+  static const int kTargets[] = {2048, 4096, 8192, 16384};
+  const int saved_algo = c->algo, saved_wg = c->tune_wg[cls], saved_stg = c->tune_stg[cls];
+  c->algo = EPRL_ALGO_RING;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    c->algo = saved_algo;
+    return hip_fail(c, hipGetLastError(), "hipEventCreate");
+  }
+  float best = 0.0f;
+  int best_wg = kRingTargetWG, best_stg = -1;
+  for (int li = 0; li < nl && rc == EPRL_OK; ++li) {
+    for (int t : kTargets) {
+      c->tune_wg[cls] = t;
+      c->tune_stg[cls] = levels[li];
+      rc = vertex_range_impl(c, two_j, dl, 1.0, B, 0, p.nshell, 0, A);  // warm-up
+      if (rc) break;
+      hipError_t e = hipEventRecord(e0, c->stream);
+      if (e == hipSuccess) rc = vertex_range_impl(c, two_j, dl, 1.0, B, 0, p.nshell, 0, A);
+      if (rc) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rc = hip_fail(c, e, "autotune timing");
+        break;
+      }
+      if (best == 0.0f || ms < best) {
+        best = ms;
+        best_wg = t;
+        best_stg = levels[li];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->algo = saved_algo;
+  if (rc) {
+    c->tune_wg[cls] = saved_wg;
+    c->tune_stg[cls] = saved_stg;
+    return rc;
+  }
+  c->tune_wg[cls] = best_wg;
+  c->tune_stg[cls] = best_stg;
+  out[0] = cls;
+  out[1] = best_wg;
+  out[2] = best_stg;
   return EPRL_OK;
 }
 

@@ -126,13 +126,16 @@ int ring_class(int DI, int DK, int KW);
 constexpr size_t kRingMaxPartialBytes = size_t(256) << 20;
 int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds);
 int ring_row_blocks(int cls);
-size_t ring_smem_bytes(int cls, int nd);
+// LDS bytes of the tile class at nd with staging level stg (-1: the most that fits).
+size_t ring_smem_bytes(int cls, int nd, int stg = -1);
+// Booster staging levels of the tile class that fit in LDS at nd, most first; returns their count.
+int ring_stage_levels(int cls, int nd, int levels[3]);
 // Largest dl + 1 the ring kernels stage booster blocks for.
 constexpr int kRingMaxNd = 16;
 hipError_t ring_init_attributes();
-hipError_t launch_ring(const RingParams &rp, int cls, hipStream_t s);
+hipError_t launch_ring(const RingParams &rp, int cls, int stg, hipStream_t s);
 hipError_t launch_ring_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems, int cls,
-                             int max_nd, int grid, int *next, hipStream_t s);
+                             int max_nd, int stg, int grid, int *next, hipStream_t s);
 hipError_t launch_reset_counters(int *c, int n, hipStream_t s);
 hipError_t launch_shell_fifteenj(const VertexParams &vp, int64_t shell, double *W,
                                  hipStream_t s);

@@ -487,6 +487,7 @@ __global__ void reset_counters(int *c, int n) {
 
 template <int DI, int DK, int KW, int STG>
 struct RingVariant {
+  static constexpr int stg = STG;
   static constexpr size_t smem(int nd) {
     const size_t stage = (size_t)(STG == 2 ? 4 : 2 * STG) * nd * (DI * DK + 2);
     return sizeof(double) * ((size_t)(64 * (KW + 1) + KW * (DI * DI + 8) + KW * (KW == 32 ? KW + 8 : KW)) +
@@ -521,8 +522,11 @@ static_assert(RingVariant<8, 16, 32, 2>::fits(kRingMaxNd) && RingVariant<8, 8, 3
 static_assert(RingVariant<16, 16, 32, 0>::fits(kRingMaxNd), "16-wide tiles must fit unstaged");
 
 // Staging level for a 16-wide tile class at nd: the most booster blocks that fit in LDS.
+// (stg = 0, 1 or 2 asks for that level when it fits; -1 takes the most that fits.)
 template <int DI, int DK, int KW, typename F>
-hipError_t pick_stage(int nd, F &&f) {
+hipError_t pick_stage(int nd, F &&f, int stg = -1) {
+  if (stg == 0) return f(RingVariant<DI, DK, KW, 0>());
+  if (stg == 1 && RingVariant<DI, DK, KW, 1>::fits(nd)) return f(RingVariant<DI, DK, KW, 1>());
   if (RingVariant<DI, DK, KW, 2>::fits(nd)) return f(RingVariant<DI, DK, KW, 2>());
   if (RingVariant<DI, DK, KW, 1>::fits(nd)) return f(RingVariant<DI, DK, KW, 1>());
   return f(RingVariant<DI, DK, KW, 0>());
@@ -531,7 +535,7 @@ hipError_t pick_stage(int nd, F &&f) {
 // Dispatch over the eight tile classes (and, for 16-wide tiles, the staging level at nd).
 // 8-wide tiles always stage all four blocks; nd = 0 visits every variant (attribute set-up).
 template <typename F>
-hipError_t dispatch(int cls, int nd, F &&f) {
+hipError_t dispatch(int cls, int nd, F &&f, int stg = -1) {
   if (nd == 0 && cls >= 4) {
     hipError_t e = hipSuccess;
     auto all = [&](auto v0, auto v1, auto v2) {
@@ -552,10 +556,10 @@ hipError_t dispatch(int cls, int nd, F &&f) {
     case 1: return f(RingVariant<8, 8, 32, 2>());
     case 2: return f(RingVariant<8, 16, 16, 2>());
     case 3: return f(RingVariant<8, 16, 32, 2>());
-    case 4: return pick_stage<16, 8, 16>(nd, f);
-    case 5: return pick_stage<16, 8, 32>(nd, f);
-    case 6: return pick_stage<16, 16, 16>(nd, f);
-    case 7: return pick_stage<16, 16, 32>(nd, f);
+    case 4: return pick_stage<16, 8, 16>(nd, f, stg);
+    case 5: return pick_stage<16, 8, 32>(nd, f, stg);
+    case 6: return pick_stage<16, 16, 16>(nd, f, stg);
+    case 7: return pick_stage<16, 16, 32>(nd, f, stg);
     default: return hipErrorInvalidValue;
   }
 }
@@ -569,13 +573,36 @@ int ring_class(int DI, int DK, int KW) {
 
 int ring_row_blocks(int cls) { return cls >= 4 ? 4 : 1; }
 
-size_t ring_smem_bytes(int cls, int nd) {
+size_t ring_smem_bytes(int cls, int nd, int stg) {
   size_t out = 0;
-  dispatch(cls, nd, [&](auto v) {
-    out = decltype(v)::smem(nd);
-    return hipSuccess;
-  });
+  dispatch(
+      cls, nd,
+      [&](auto v) {
+        out = decltype(v)::smem(nd);
+        return hipSuccess;
+      },
+      stg);
   return out;
+}
+
+int ring_stage_levels(int cls, int nd, int levels[3]) {
+  if (cls < 4) {
+    levels[0] = 2;
+    return 1;
+  }
+  int n = 0;
+  for (int stg = 2; stg >= 0; --stg) {
+    int got = -1;
+    dispatch(
+        cls, nd,
+        [&](auto v) {
+          got = decltype(v)::stg;
+          return hipSuccess;
+        },
+        stg);
+    if (got == stg) levels[n++] = stg;
+  }
+  return n;
 }
 
 // Allow the ring kernels the dynamic LDS of the largest supported configuration.  Called once
@@ -588,16 +615,20 @@ hipError_t ring_init_attributes() {
   return hipSuccess;
 }
 
-hipError_t launch_ring(const RingParams &rp, int cls, hipStream_t s) {
-  return dispatch(cls, rp.nd, [&](auto v) { return decltype(v)::launch(rp, s); });
+hipError_t launch_ring(const RingParams &rp, int cls, int stg, hipStream_t s) {
+  return dispatch(
+      cls, rp.nd, [&](auto v) { return decltype(v)::launch(rp, s); }, stg);
 }
 
 hipError_t launch_ring_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems, int cls,
-                             int max_nd, int grid, int *next, hipStream_t s) {
+                             int max_nd, int stg, int grid, int *next, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  return dispatch(cls, max_nd, [&](auto v) {
-    return decltype(v)::launch_batch(cfgs_dev, items_dev, nitems, max_nd, grid, next, s);
-  });
+  return dispatch(
+      cls, max_nd,
+      [&](auto v) {
+        return decltype(v)::launch_batch(cfgs_dev, items_dev, nitems, max_nd, grid, next, s);
+      },
+      stg);
 }
 
 hipError_t launch_reset_counters(int *c, int n, hipStream_t s) {

@@ -351,6 +351,33 @@ def test_batched_large_spins(lib, torch):
         assert torch.equal(outs[c], lib.vertex_tensor(tj, dl, 1.2, bds[c]))
 
 
+@pytest.mark.parametrize("two_j,dl,seed", [([4, 1, 1, 4, 4, 3, 3, 1, 4, 1], 3, 21),
+                                          ([13, 10, 11, 12, 10, 14, 11, 13, 13, 10], 1, 22)])
+def test_autotune(lib, torch, two_j, dl, seed):
+    """The autotuner keeps a valid setting for the configuration's tile class; with it the tensor
+    still matches the oracle, repeats bitwise and equals the batched result."""
+    b, bd = boosters_for(torch, two_j, dl, seed)
+    cls = lib.count_work(two_j, dl)["ring_class"]
+    note(f"autotune {two_j} dl={dl} (tile class {cls})")
+    res = lib.autotune(two_j, dl, bd)
+    try:
+        note(f"  chosen {res}")
+        assert res["tile_class"] == cls
+        assert res["target_workgroups"] in (2048, 4096, 8192, 16384)
+        assert res["staging_level"] in ((2,) if cls < 4 else (0, 1, 2))
+        a = lib.vertex_tensor(two_j, dl, 1.2, bd)
+        assert torch.equal(a, lib.vertex_tensor(two_j, dl, 1.2, bd))
+        assert normwise(a.cpu().numpy(), V.vertex_tensor(two_j, dl, b)) <= TOL
+        (batched,) = lib.vertex_tensor_batched([(two_j, dl)], 1.2, [bd])
+        assert torch.equal(batched, a)
+        with pytest.raises(lib.EprlError):
+            lib.set_tuning(8, 0, -1)
+        with pytest.raises(lib.EprlError):
+            lib.set_tuning(cls, 0, 3)
+    finally:
+        lib.set_tuning(cls, 0, -1)
+
+
 def test_batched_equals_plain(lib, torch):
     configs = workloads.cfg3_batch()[:6]
     configs = [(tj, min(dl, 2)) for tj, dl in configs]
