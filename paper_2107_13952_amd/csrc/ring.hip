@@ -86,6 +86,9 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
   d4v acc[CT];
 #pragma unroll
   for (int cb = 0; cb < CT; ++cb) acc[cb] = d4v{0.0, 0.0, 0.0, 0.0};
+  // The two pad entries after each staged booster block are read (times zero) by the
+  // branch-free step 1 and never written by the staging: clear them once.
+  for (int q = tid; q < NBLK * nd; q += RT) Mb[q * MBS + DI * DK] = Mb[q * MBS + DI * DK + 1] = 0.0;
 
   const int64_t c0 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index];
   const int64_t c1 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index + 1];
@@ -135,8 +138,10 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
       // Weighted booster blocks (2k+1) B of this core: e = 0 M5, 1 M4 (per l45), 2 M2, 3 M3
       // (per l23); rows i, columns k relative to the lowest k of the block; zero outside the
       // block, pads included (reads below run past a row end and multiply by zero there).
-      for (int idx = tid; idx < NBLK * nd * MBS; idx += RT) {
-        const int blk = idx / (nd * MBS), o = (idx / MBS) % nd, r = idx % MBS;
+      constexpr int BS = DI * DK;  // entries of a block (a power of two; its pads stay zero)
+      for (int idx = tid; idx < NBLK * nd * BS; idx += RT) {
+        const int bi = idx / BS, r = idx % BS;
+        const int blk = bi / nd, o = bi - blk * nd;
         const int e = STG == 2 ? blk : (blk == 0 ? 1 : 3);
         const int i = r / DK, k = r % DK;
         const int lo = rng[(e == 0 ? 0 : e == 1 ? 2 : e == 2 ? 4 : 6) * nd + o];
@@ -144,7 +149,7 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
         const int ni = e == 0 ? d5 : e == 1 ? d4 : e == 2 ? d2 : d3;
         double v = 0.0;
         if (i < ni && k < kn) v = B[bo[e * nd + o] + (int64_t)i * kn + k] * (double)(lo + 2 * k + 1);
-        Mb[idx] = v;
+        Mb[bi * MBS + r] = v;
       }
     }
     // x closes (i1 l25 x); the other triads restrict the k ranges at each x.
