@@ -49,6 +49,10 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
   constexpr bool STAGE = STG == 2;   // M5, M2 in LDS (first stage)
   constexpr bool STAGE2 = STG >= 1;  // M4, M3 in LDS (second stage)
   constexpr int NBLK = STG == 2 ? 4 : 2 * STG;
+  // 8-wide tiles (always fully staged) look up the step-2 operands of each (l45, k4) and
+  // (l23, k3) in a per-core table instead of testing the k ranges per l45 / l23.
+  constexpr bool TAB = DI == 8 && STAGE2;
+  constexpr int ZN = TAB ? 8 * DK : 0;  // zero column read by table entries of inactive spins
   constexpr int GS = KW + 1;       // padded row stride of G and P
   constexpr int CC = DI * DI;      // columns (i3, i2)
   constexpr int CT = CC / 16;      // column tiles
@@ -66,10 +70,14 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
   double *T5 = U3s + KW * U3S;        // [nd][T5S] per l45: sum_k5 U1 M5 U2 as [i5 of block][k4]
   double *T2 = T5 + nd * T5S;         // [nd][T2S] per l23: sum_k2 U4 M2 U5 as [i2][k3]
   double *Mb = T2 + nd * T2S;         // [NBLK][nd][MBS] weighted boosters as [i][k]
-  int64_t *bo = reinterpret_cast<int64_t *>(Mb + NBLK * nd * MBS);  // [4][nd]
+  double *Zc = Mb + NBLK * nd * MBS;  // [ZN] zeros
+  int64_t *bo = reinterpret_cast<int64_t *>(Zc + ZN);  // [4][nd]
   // Offset in Mb of the block of edge slot e (0 M5, 1 M4, 2 M2, 3 M3) for the spin index o.
   auto mb = [&](int e, int o) { return ((STG == 2 ? e : (e == 1 ? 0 : 1)) * nd + o) * MBS; };
-  int *rng = reinterpret_cast<int *>(bo + 4 * nd);           // [8][nd] lo/n of k5, k4, k2, k3
+  // [2][nd][KW] step-2 table: LDS byte offsets of the T5 (T2) entry and the M4 (M3) column of
+  // spin index o at window position k4l (k3l); inactive pairs point at the zero column.
+  int2 *tab = reinterpret_cast<int2 *>(bo + 4 * nd);
+  int *rng = reinterpret_cast<int *>(tab + (TAB ? 2 * nd * KW : 0));  // [8][nd] lo/n of k5, k4, k2, k3
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int *J = rp.two_j;
@@ -89,6 +97,7 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
   // The two pad entries after each staged booster block are read (times zero) by the
   // branch-free step 1 and never written by the staging: clear them once.
   for (int q = tid; q < NBLK * nd; q += RT) Mb[q * MBS + DI * DK] = Mb[q * MBS + DI * DK + 1] = 0.0;
+  for (int q = tid; q < ZN; q += RT) Zc[q] = 0.0;
 
   const int64_t c0 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index];
   const int64_t c1 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index + 1];
@@ -134,6 +143,21 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
       }
     }
     if (w4hi < 0 || w3hi < 0) continue;  // uniform: no live shell in this core
+    if (TAB) {
+      // Entry (side, o, kl): k4 = w4lo + 2 kl against the k4 range of l45 = o (side 0), or
+      // k3 = w3lo + 2 kl against the k3 range of l23 = o (side 1); read after the x loop's
+      // first barrier.
+      for (int q = tid; q < 2 * nd * KW; q += RT) {
+        const int side = q / (nd * KW), o = (q / KW) % nd, kl = q % KW;
+        const int kk = (side == 0 ? w4lo : w3lo) + 2 * kl;
+        const int nf = rng[(side == 0 ? 1 : 5) * nd + o], lo = rng[(side == 0 ? 2 : 6) * nd + o];
+        const int n = rng[(side == 0 ? 3 : 7) * nd + o], ki = (kk - lo) >> 1;
+        const bool ok = nf > 0 && kk >= lo && ki < n;
+        const double *tv = ok ? (side == 0 ? T5 + o * T5S : T2 + o * T2S) + ki : Zc;
+        const double *mv = Mb + mb(side == 0 ? 1 : 3, o) + (ok ? ki : 0);
+        tab[q] = int2{(int)((tv - smem) * sizeof(double)), (int)((mv - smem) * sizeof(double))};
+      }
+    }
     if (STG > 0) {
       // Weighted booster blocks (2k+1) B of this core: e = 0 M5, 1 M4 (per l45), 2 M2, 3 M3
       // (per l23); rows i, columns k relative to the lowest k of the block; zero outside the
@@ -338,7 +362,19 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
           double g[DI];
 #pragma unroll
           for (int q = 0; q < DI; ++q) g[q] = 0.0;
-          if (k4l >= a4l && k4l <= b4l && i5 < d5) {
+          if (TAB && k4l >= a4l && k4l <= b4l && i5 < d5) {
+            const int2 *te = tab + k4l;
+            const char *sb = reinterpret_cast<const char *>(smem);
+            const int tr = i5l * DK * (int)sizeof(double);
+#pragma unroll 2
+            for (int o = 0; o < nd; ++o) {
+              const int2 e = te[o * KW];
+              const double t = *reinterpret_cast<const double *>(sb + e.x + tr);
+              const double *m4 = reinterpret_cast<const double *>(sb + e.y);
+#pragma unroll
+              for (int i4 = 0; i4 < DI; ++i4) g[i4] += t * m4[i4 * DK];
+            }
+          } else if (!TAB && k4l >= a4l && k4l <= b4l && i5 < d5) {
             const int k4 = w4lo + 2 * k4l;
 #pragma unroll 2
             for (int o = 0; o < nd; ++o) {
@@ -370,7 +406,19 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
           double hq[DI];
 #pragma unroll
           for (int q = 0; q < DI; ++q) hq[q] = 0.0;
-          if (k3l >= a3l && k3l <= b3l && i2 < d2) {
+          if (TAB && k3l >= a3l && k3l <= b3l && i2 < d2) {
+            const int2 *te = tab + nd * KW + k3l;
+            const char *sb = reinterpret_cast<const char *>(smem);
+            const int tr = i2 * DK * (int)sizeof(double);
+#pragma unroll 2
+            for (int o = 0; o < nd; ++o) {
+              const int2 e = te[o * KW];
+              const double t = *reinterpret_cast<const double *>(sb + e.x + tr);
+              const double *m3 = reinterpret_cast<const double *>(sb + e.y);
+#pragma unroll
+              for (int i3 = 0; i3 < DI; ++i3) hq[i3] += t * m3[i3 * DK];
+            }
+          } else if (!TAB && k3l >= a3l && k3l <= b3l && i2 < d2) {
             const int k3 = w3lo + 2 * k3l;
 #pragma unroll 2
             for (int o = 0; o < nd; ++o) {
@@ -495,9 +543,11 @@ struct RingVariant {
   static constexpr int stg = STG;
   static constexpr size_t smem(int nd) {
     const size_t stage = (size_t)(STG == 2 ? 4 : 2 * STG) * nd * (DI * DK + 2);
+    const bool tab = DI == 8 && STG >= 1;
     return sizeof(double) * ((size_t)(64 * (KW + 1) + KW * (DI * DI + 8) + KW * (KW == 32 ? KW + 8 : KW)) +
-                             (size_t)nd * ((64 / DI + DI) * DK + 16) + stage) +
-           sizeof(int64_t) * (size_t)(4 * nd) + sizeof(int) * (size_t)(8 * nd);
+                             (size_t)nd * ((64 / DI + DI) * DK + 16) + stage + (tab ? 8 * DK : 0)) +
+           sizeof(int64_t) * (size_t)(4 * nd) + 2 * sizeof(int) * (size_t)(tab ? 2 * nd * KW : 0) +
+           sizeof(int) * (size_t)(8 * nd);
   }
   static constexpr bool fits(int nd) { return smem(nd) <= kLdsBytes; }
   static hipError_t init() {
