@@ -40,6 +40,18 @@ __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
+// An empty asm taking the N values as register operands: the LDS reads that produce them are
+// all issued before the first use, rather than one by one between the multiply-adds that the
+// register-frugal schedule would otherwise interleave them with (one wait instead of N / 2).
+template <int N>
+__device__ __forceinline__ void ready(double (&v)[N]) {
+  static_assert(N % 8 == 0, "groups of eight");
+#pragma unroll
+  for (int g = 0; g < N; g += 8)
+    asm volatile("" : "+v"(v[g]), "+v"(v[g + 1]), "+v"(v[g + 2]), "+v"(v[g + 3]), "+v"(v[g + 4]),
+                 "+v"(v[g + 5]), "+v"(v[g + 6]), "+v"(v[g + 7]));
+}
+
 // One work item: cores [bounds[i1][chunk], bounds[i1][chunk + 1]) of rp, boundary intertwiner
 // i1 = n1, row block rb (rows rb * 64 .. rb * 64 + 63 of A(i1; rows, cols)).
 // STG: booster blocks of a core staged in LDS: 2 all four (M5, M4, M2, M3), 1 the two read in
@@ -269,8 +281,12 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
         double t = 0.0;
         if (STAGE) {
           const double *m = Mb + mb(e, o) + i * DK + kk0;
+          double mv[DK];
 #pragma unroll
-          for (int q = 0; q < DK; ++q) t += a[q] * m[q];
+          for (int q = 0; q < DK; ++q) mv[q] = m[q];
+          ready(mv);
+#pragma unroll
+          for (int q = 0; q < DK; ++q) t += a[q] * mv[q];
         } else if (c > 0 && i < ni) {
           const int kn = rng[(e == 0 ? 1 : 5) * nd + o];
           const double *m = B + bo[e * nd + o] + (int64_t)i * kn + kk0;
@@ -366,13 +382,21 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
             const int2 *te = tab + k4l;
             const char *sb = reinterpret_cast<const char *>(smem);
             const int tr = i5l * DK * (int)sizeof(double);
-#pragma unroll 2
+            int2 e = te[0];
             for (int o = 0; o < nd; ++o) {
-              const int2 e = te[o * KW];
+              // One LDS round trip per spin: this spin's operands and the next spin's table
+              // entry are all in flight before the first multiply-add.
               const double t = *reinterpret_cast<const double *>(sb + e.x + tr);
               const double *m4 = reinterpret_cast<const double *>(sb + e.y);
+              double mv[DI];
 #pragma unroll
-              for (int i4 = 0; i4 < DI; ++i4) g[i4] += t * m4[i4 * DK];
+              for (int q = 0; q < DI; ++q) mv[q] = m4[q * DK];
+              int2 en = te[(o + 1 < nd ? o + 1 : o) * KW];
+              ready(mv);
+              asm volatile("" : "+v"(en.x), "+v"(en.y));
+#pragma unroll
+              for (int q = 0; q < DI; ++q) g[q] += t * mv[q];
+              e = en;
             }
           } else if (!TAB && k4l >= a4l && k4l <= b4l && i5 < d5) {
             const int k4 = w4lo + 2 * k4l;
@@ -410,13 +434,21 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
             const int2 *te = tab + nd * KW + k3l;
             const char *sb = reinterpret_cast<const char *>(smem);
             const int tr = i2 * DK * (int)sizeof(double);
-#pragma unroll 2
+            int2 e = te[0];
             for (int o = 0; o < nd; ++o) {
-              const int2 e = te[o * KW];
+              // One LDS round trip per spin: this spin's operands and the next spin's table
+              // entry are all in flight before the first multiply-add.
               const double t = *reinterpret_cast<const double *>(sb + e.x + tr);
               const double *m3 = reinterpret_cast<const double *>(sb + e.y);
+              double mv[DI];
 #pragma unroll
-              for (int i3 = 0; i3 < DI; ++i3) hq[i3] += t * m3[i3 * DK];
+              for (int q = 0; q < DI; ++q) mv[q] = m3[q * DK];
+              int2 en = te[(o + 1 < nd ? o + 1 : o) * KW];
+              ready(mv);
+              asm volatile("" : "+v"(en.x), "+v"(en.y));
+#pragma unroll
+              for (int q = 0; q < DI; ++q) hq[q] += t * mv[q];
+              e = en;
             }
           } else if (!TAB && k3l >= a3l && k3l <= b3l && i2 < d2) {
             const int k3 = w3lo + 2 * k3l;
