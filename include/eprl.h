@@ -95,7 +95,8 @@ int eprl_set_tuning(eprl_ctx *ctx, int tile_class, int target_workgroups, int st
 
 /* Autotuner: times the vertex tensor of this configuration (boosters device, A device scratch
  * of prod(dims_i) doubles, overwritten) in the factorised order for target workgroups
- * 2048, 4096, 8192, 16384 and every staging level that fits, keeps the fastest setting for
+ * 2048, 4096, 8192, 16384 and every staging level that fits (one warm-up call, then the
+ * fastest of three timed calls per setting), keeps the fastest setting for
  * the configuration's tile class on this context (as eprl_set_tuning would) and writes
  * out[0] = tile class, out[1] = target workgroups, out[2] = staging level.  Synchronises the
  * context's stream.  EPRL_ERANGE when the factorised order does not apply. */
