@@ -60,6 +60,18 @@ def cpu_baseline(two_j, dl, boosters_np, nshell_sample):
                       f"{terms:.3g} terms in {dt:.1f} s, one thread"}
 
 
+def quadrature_boosters(two_j, dl, size):
+    """The FP64 quadrature boosters of eq. (booster) at gamma = 1.2 stored beside the oracle's
+    j = 3, dl = 8 vertex rows (written offline by tests/golden/make_golden.py), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "vertex_j3_dl8_phys.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    if list(g["two_j"]) != list(two_j) or int(g["dl"]) != dl or g["boosters"].size != size:
+        return None
+    return np.ascontiguousarray(g["boosters"], dtype=np.float64)
+
+
 def measured_traffic(split=None):
     """HBM bytes per ring_kernel launch from the committed counter summary, when it was taken on
     the current kernel source (same sha256 prefix) with the work split timed here (default:
@@ -226,7 +238,10 @@ def main():
     dims, ilo, offs = lib.layout(two_j, dl)
     shapes = [(dims[e + 1], int((offs[e * (dl + 1) ** 3 + t + 1] - offs[e * (dl + 1) ** 3 + t]) // dims[e + 1]))
               for e in range(4) for t in range((dl + 1) ** 3)]
-    b_np = workloads.synthetic_boosters(cfg["booster_seed"], shapes)
+    b_np = quadrature_boosters(two_j, dl, int(offs[-1]))
+    physical = b_np is not None
+    if not physical:
+        b_np = workloads.synthetic_boosters(cfg["booster_seed"], shapes)
     b = torch.from_numpy(b_np).to(dev)
     live, terms = lib.count_terms(two_j, dl)
     work = lib.count_work(two_j, dl)
@@ -258,8 +273,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic: seeded N(0,1)/dim(k) boosters of the exact packed shape (A is "
-                "multilinear in them; the work does not depend on their values)",
+        "data": ("synthetic spins; boosters from the FP64 quadrature of eq. (booster) at "
+                 "gamma=1.2 (stored oracle output)" if physical else
+                 "synthetic: seeded N(0,1)/dim(k) boosters of the exact packed shape (A is "
+                 "multilinear in them; the work does not depend on their values)"),
         "config": {"workload": "plain EPRL vertex tensor, equilateral j=3 (two_j=6), dl=8, "
                                "gamma=1.2, intertwiners 0..6 (7^5 FP64 tensor)",
                    "two_j": two_j, "dl": dl, "live_shells": live, "terms": terms,

@@ -2,7 +2,9 @@
 
 Calls only the oracle and the seeded input generators.  Output: ``vertex_<name>.npz`` with the
 spins, dl, the booster seed, the i1 rows computed (all of them unless a reduced boundary-
-intertwiner range is asked for) and A[rows, i2..i5] (float64).  The shell sum is split over worker
+intertwiner range is asked for) and A[rows, i2..i5] (float64).  Entries with physical boosters
+(the oracle's FP64 quadrature of eq. (booster) at gamma = 1.2) also store those boosters
+(booster_seed -1).  The shell sum is split over worker
 processes by contiguous shell ranges and the partial tensors are summed in range order.
 
     python tests/golden/make_golden.py               # every entry of GOLDEN (about 30 min, 8 cores)
@@ -19,8 +21,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import workloads as W  # noqa: E402
+from oracle import boosters as B  # noqa: E402
 from oracle import ranges as R  # noqa: E402
 from oracle import vertex as V  # noqa: E402
+
+GAMMA = 1.2
 
 
 def _batch_entry(name, batch, seed, c, rows=None, dl=None):
@@ -43,6 +48,10 @@ def _registry():
     for c, rows in ((0, [0, 10]), (3, [5, 13])):
         g.update([_batch_entry(f"b5_c{c:02d}_rows", b5, W.CFG5_SEED, c, rows)])
     g.update([_batch_entry("b5_c00_dl2", b5, W.CFG5_SEED, 0, None, dl=2)])
+    # Physical boosters: the j = 1, dl = 3 vertex in full and the j = 3, dl = 8 vertex on its
+    # first and last i1 rows.
+    g["j1_dl3_phys"] = dict(two_j=W.CFG1["two_j"], dl=W.CFG1["dl"], booster_seed=-1, rows=None)
+    g["j3_dl8_phys"] = dict(two_j=W.CFG2["two_j"], dl=W.CFG2["dl"], booster_seed=-1, rows=[0, 6])
     return g
 
 
@@ -50,8 +59,7 @@ GOLDEN = _registry()
 
 
 def _part(args):
-    two_j, dl, seed, rows, lo, hi = args
-    b = W.synthetic_boosters(seed, R.block_shapes(two_j, dl))
+    two_j, dl, b, rows, lo, hi = args
     return V.vertex_tensor(two_j, dl, b, shells=R.all_shells(dl)[lo:hi], i1_rows=rows)
 
 
@@ -61,7 +69,12 @@ def make(name, procs=8, pieces=64):
     n = (dl + 1) ** 6
     pieces = min(pieces, n)
     bounds = [n * q // pieces for q in range(pieces + 1)]
-    jobs = [(two_j, dl, seed, rows, bounds[q], bounds[q + 1]) for q in range(pieces)]
+    if seed < 0:
+        b, imag, err = B.boosters(two_j, dl, GAMMA)
+        assert imag <= 1e-14 * np.abs(b).max() and err <= 1e-13 * np.abs(b).max(), (imag, err)
+    else:
+        b = W.synthetic_boosters(seed, R.block_shapes(two_j, dl))
+    jobs = [(two_j, dl, b, rows, bounds[q], bounds[q + 1]) for q in range(pieces)]
     with Pool(procs) as pool:
         parts = pool.map(_part, jobs)
     a = np.zeros_like(parts[0])
@@ -69,8 +82,9 @@ def make(name, procs=8, pieces=64):
         a += p
     nrow = R.boundary_ranges(two_j)[0][1]
     out = os.path.join(HERE, f"vertex_{name}.npz")
+    extra = dict(boosters=b, gamma=GAMMA) if seed < 0 else {}
     np.savez_compressed(out, two_j=np.array(two_j), dl=dl, booster_seed=seed,
-                        rows=np.arange(nrow) if rows is None else np.array(rows), A=a)
+                        rows=np.arange(nrow) if rows is None else np.array(rows), A=a, **extra)
     return out
 
 

@@ -290,10 +290,14 @@ STORED = [n for n in GOLDEN if n != workloads.CFG2["name"]]
 @pytest.mark.parametrize("name", STORED)
 def test_stored_oracle_tensor(lib, torch, algo, name):
     """Irregular spins (every tile class), j = 4 and large-spin vertices at full size against
-    oracle tensors written offline (all i1 rows, or a reduced i1 range for the largest)."""
+    oracle tensors written offline (all i1 rows, or a reduced i1 range for the largest); the
+    j = 1 and j = 3 vertices also with the oracle's quadrature boosters (stored with them)."""
     e = GOLDEN[name]
     g = load_golden(name)
-    b, bd = boosters_for(torch, e["two_j"], e["dl"], e["booster_seed"])
+    if e["booster_seed"] < 0:
+        bd = torch.from_numpy(np.ascontiguousarray(g["boosters"])).cuda()
+    else:
+        b, bd = boosters_for(torch, e["two_j"], e["dl"], e["booster_seed"])
     note(f"{name} [{algo}] two_j={e['two_j']} dl={e['dl']}")
     a = vertex_or_skip(lib, algo, e["two_j"], e["dl"], 1.2, bd).cpu().numpy()
     err = normwise(a[g["rows"]], g["A"])
