@@ -192,11 +192,14 @@ def time_steps(lib, torch, two_j, dl, b, out, steps, warmup, kernel):
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
+    t0 = time.perf_counter()
     for _ in range(steps):
         lib.vertex_tensor(two_j, dl, 1.2, b, out=out)
+    host_ms = (time.perf_counter() - t0) * 1e3 / steps
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
+    progress(f"host time per call (enqueue) {host_ms:.3f} ms")
     kms, kn = lib.timing_read(kernel)
     tab_ms, tab_n = lib.timing_read("sixj_tables")
     red_ms, red_n = lib.timing_read("reduce")
@@ -212,6 +215,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-shells", type=int, default=3000, help="oracle sample size (0 = skip)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--synthetic-boosters", action="store_true",
+                    help="seeded random boosters instead of the stored quadrature boosters")
     ap.add_argument("--no-paper-order", action="store_true", help="skip timing the per-shell order")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default work split instead of the autotuned one")
@@ -238,7 +243,7 @@ def main():
     dims, ilo, offs = lib.layout(two_j, dl)
     shapes = [(dims[e + 1], int((offs[e * (dl + 1) ** 3 + t + 1] - offs[e * (dl + 1) ** 3 + t]) // dims[e + 1]))
               for e in range(4) for t in range((dl + 1) ** 3)]
-    b_np = quadrature_boosters(two_j, dl, int(offs[-1]))
+    b_np = None if args.synthetic_boosters else quadrature_boosters(two_j, dl, int(offs[-1]))
     physical = b_np is not None
     if not physical:
         b_np = workloads.synthetic_boosters(cfg["booster_seed"], shapes)

@@ -42,6 +42,10 @@ struct eprl_ctx {
   // most that fits).
   int tune_wg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int tune_stg[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  // Cost schedule of the last configuration run in the factorised order (host data only; it
+  // depends on the spins, dl and the workgroup target, and is recomputed when they change).
+  std::vector<int> sched_key, sched_bounds;
+  int sched_nchunk = 0;
   // Batched path: a dedicated workspace and the instantiated graph of the last batch.
   struct Batch {
     std::vector<int64_t> key;
@@ -303,9 +307,17 @@ ReduceParams reduce_params(const Plan &p, const double *partial, int nchunk, dou
 // Factorised evaluation over all shells (one launch of the ring kernel, then the reduction).
 int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int accumulate,
               double *A, const Plan &probe) {
-  std::vector<int> bounds;
   const int cls = probe.ring_cls;
-  const int nchunk = ring_schedule(probe, c->tune_wg[cls] > 0 ? c->tune_wg[cls] : kRingTargetWG, bounds);
+  const int target = c->tune_wg[cls] > 0 ? c->tune_wg[cls] : kRingTargetWG;
+  std::vector<int> key(two_j, two_j + 10);
+  key.push_back(dl);
+  key.push_back(target);
+  if (key != c->sched_key) {
+    c->sched_nchunk = ring_schedule(probe, target, c->sched_bounds);
+    c->sched_key = key;
+  }
+  const std::vector<int> &bounds = c->sched_bounds;
+  const int nchunk = c->sched_nchunk;
   const size_t pbytes = align_up((size_t)nchunk * probe.a_size * sizeof(double), 256);
   Prepared prep;
   int rc = prepare(c, two_j, dl, pbytes, prep, true, &bounds);
