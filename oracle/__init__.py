@@ -15,6 +15,9 @@ amplitudes", arXiv:2107.13952) defines, used only to check the HIP library:
                  as in the framed algorithm of Sec. 3.1 (steps 5-7).
 * ``contract`` - the contraction of A with five boundary vectors (Sec. 3.2, the
                  ``contract`` call) and its derivatives.
+* ``boosters`` - the booster functions of eq. (booster) by FP64 quadrature (Sec. 3.1,
+                 "Booster coefficients"): the input the library takes, produced for the
+                 parity cases and the benchmark.
 
 Only ``tests/``, the smoke entry point and the CPU-baseline leg of the benchmark may import
 it. The GPU product path never does, and this package never imports the GPU path.
