@@ -290,9 +290,12 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
         } else if (c > 0 && i < ni) {
           const int kn = rng[(e == 0 ? 1 : 5) * nd + o];
           const double *m = B + bo[e * nd + o] + (int64_t)i * kn + kk0;
+          double mv[DK];  // the row's c active entries, all reads in flight together
 #pragma unroll
-          for (int q = 0; q < DK; ++q)
-            if (q < c) t += a[q] * (m[q] * (double)(ka + 2 * q + 1));
+          for (int q = 0; q < DK; ++q) mv[q] = q < c ? m[q] : 0.0;
+          ready(mv);
+#pragma unroll
+          for (int q = 0; q < DK; ++q) t += a[q] * (mv[q] * (double)(ka + 2 * q + 1));
         }
         if (side == 0)
           T5[o * T5S + il * DK + ki] = t;
@@ -410,16 +413,23 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
                 const int kc = ok ? k4i : 0;
                 const double t = ok ? T5[o * T5S + i5l * DK + kc] : 0.0;
                 const double *m4 = Mb + mb(1, o) + kc;
+                double mv[DI];
 #pragma unroll
-                for (int i4 = 0; i4 < DI; ++i4) g[i4] += t * m4[i4 * DK];
+                for (int i4 = 0; i4 < DI; ++i4) mv[i4] = m4[i4 * DK];
+                ready(mv);
+#pragma unroll
+                for (int i4 = 0; i4 < DI; ++i4) g[i4] += t * mv[i4];
               } else {
                 if (!ok) continue;
                 const double t = T5[o * T5S + i5l * DK + k4i];
                 const double w4 = (double)(k4 + 1);
                 const double *m4 = B + bo[1 * nd + o] + k4i;
+                double mv[DI];
 #pragma unroll
-                for (int i4 = 0; i4 < DI; ++i4)
-                  if (i4 < d4) g[i4] += t * (m4[(int64_t)i4 * n4] * w4);
+                for (int i4 = 0; i4 < DI; ++i4) mv[i4] = i4 < d4 ? m4[(int64_t)i4 * n4] : 0.0;
+                ready(mv);
+#pragma unroll
+                for (int i4 = 0; i4 < DI; ++i4) g[i4] += t * (mv[i4] * w4);
               }
             }
           }
@@ -461,16 +471,23 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
                 const int kc = ok ? k3i : 0;
                 const double t = ok ? T2[o * T2S + i2 * DK + kc] : 0.0;
                 const double *m3 = Mb + mb(3, o) + kc;
+                double mv[DI];
 #pragma unroll
-                for (int i3 = 0; i3 < DI; ++i3) hq[i3] += t * m3[i3 * DK];
+                for (int i3 = 0; i3 < DI; ++i3) mv[i3] = m3[i3 * DK];
+                ready(mv);
+#pragma unroll
+                for (int i3 = 0; i3 < DI; ++i3) hq[i3] += t * mv[i3];
               } else {
                 if (!ok) continue;
                 const double t = T2[o * T2S + i2 * DK + k3i];
                 const double w3 = (double)(k3 + 1);
                 const double *m3 = B + bo[3 * nd + o] + k3i;
+                double mv[DI];
 #pragma unroll
-                for (int i3 = 0; i3 < DI; ++i3)
-                  if (i3 < d3) hq[i3] += t * (m3[(int64_t)i3 * n3] * w3);
+                for (int i3 = 0; i3 < DI; ++i3) mv[i3] = i3 < d3 ? m3[(int64_t)i3 * n3] : 0.0;
+                ready(mv);
+#pragma unroll
+                for (int i3 = 0; i3 < DI; ++i3) hq[i3] += t * (mv[i3] * w3);
               }
             }
           }
