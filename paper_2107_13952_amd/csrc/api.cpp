@@ -17,11 +17,15 @@ struct eprl_ctx {
   // grow-only device workspace
   char *ws = nullptr;
   size_t ws_size = 0;
-  // pinned staging for small host->device uploads, reused once the previous copy finished
-  char *stage = nullptr;
-  size_t stage_size = 0;
-  hipEvent_t stage_done = nullptr;
-  bool stage_pending = false;
+  // Pinned staging for small host->device uploads: a ring of buffers, each reused once its
+  // last copy has finished, so that the host waits for the device only when it runs
+  // kStages calls ahead (never in steady state), not once per call.
+  static constexpr int kStages = 8;
+  char *stage[kStages] = {};
+  size_t stage_size[kStages] = {};
+  hipEvent_t stage_done[kStages] = {};
+  bool stage_pending[kStages] = {};
+  int stage_cur = 0;
   // factorial prime-exponent table (device), valid for arguments <= fact_max
   uint16_t *fexp = nullptr;
   int *primes = nullptr;
@@ -130,32 +134,36 @@ int ensure_workspace(eprl_ctx *c, size_t bytes) {
   return EPRL_OK;
 }
 
-// Return a pinned staging area of `bytes`, waiting for the previous upload from it.
+// The next pinned staging buffer of the ring, at least `bytes` long; waits only for the last
+// upload from that buffer (kStages uploads ago).
 int staging(eprl_ctx *c, size_t bytes, char **out) {
-  if (c->stage_pending) {
-    HIP_TRY(c, hipEventSynchronize(c->stage_done));
-    c->stage_pending = false;
+  const int k = c->stage_cur = (c->stage_cur + 1) % eprl_ctx::kStages;
+  if (c->stage_pending[k]) {
+    HIP_TRY(c, hipEventSynchronize(c->stage_done[k]));
+    c->stage_pending[k] = false;
   }
-  if (bytes > c->stage_size) {
-    if (c->stage) HIP_TRY(c, hipHostFree(c->stage));
-    c->stage = nullptr;
+  if (bytes > c->stage_size[k]) {
+    if (c->stage[k]) HIP_TRY(c, hipHostFree(c->stage[k]));
+    c->stage[k] = nullptr;
     size_t want = std::max(bytes, (size_t)1 << 20);
-    if (hipHostMalloc((void **)&c->stage, want, hipHostMallocDefault) != hipSuccess) {
-      c->stage = nullptr;
-      c->stage_size = 0;
+    if (hipHostMalloc((void **)&c->stage[k], want, hipHostMallocDefault) != hipSuccess) {
+      c->stage[k] = nullptr;
+      c->stage_size[k] = 0;
       (void)hipGetLastError();
       return fail(c, EPRL_ENOMEM, "pinned staging allocation failed");
     }
-    c->stage_size = want;
+    c->stage_size[k] = want;
   }
-  *out = c->stage;
+  *out = c->stage[k];
   return EPRL_OK;
 }
 
+// Copies the first `bytes` of the current staging buffer to dst and marks it in flight.
 int upload(eprl_ctx *c, void *dst, size_t bytes) {
-  HIP_TRY(c, hipMemcpyAsync(dst, c->stage, bytes, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipEventRecord(c->stage_done, c->stream));
-  c->stage_pending = true;
+  const int k = c->stage_cur;
+  HIP_TRY(c, hipMemcpyAsync(dst, c->stage[k], bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipEventRecord(c->stage_done[k], c->stream));
+  c->stage_pending[k] = true;
   return EPRL_OK;
 }
 
@@ -648,8 +656,8 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
       so += b.second;
     }
   }
-  HIP_TRY(c, hipEventRecord(c->stage_done, c->stream));
-  c->stage_pending = true;
+  HIP_TRY(c, hipEventRecord(c->stage_done[c->stage_cur], c->stream));
+  c->stage_pending[c->stage_cur] = true;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int ncu = 256;
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
@@ -736,9 +744,13 @@ int eprl_create(eprl_ctx **out, int device, void *hip_stream) {
   if (!c) return EPRL_ENOMEM;
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  if (hipSetDevice(device) != hipSuccess || ring_init_attributes() != hipSuccess ||
-      hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
+  bool ok = hipSetDevice(device) == hipSuccess && ring_init_attributes() == hipSuccess;
+  for (int k = 0; ok && k < eprl_ctx::kStages; ++k)
+    ok = hipEventCreateWithFlags(&c->stage_done[k], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
     (void)hipGetLastError();
+    for (int k = 0; k < eprl_ctx::kStages; ++k)
+      if (c->stage_done[k]) (void)hipEventDestroy(c->stage_done[k]);
     delete c;
     return EPRL_EHIP;
   }
@@ -752,10 +764,12 @@ void eprl_destroy(eprl_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   if (c->ws) (void)hipFree(c->ws);
-  if (c->stage) (void)hipHostFree(c->stage);
+  for (int k = 0; k < eprl_ctx::kStages; ++k) {
+    if (c->stage[k]) (void)hipHostFree(c->stage[k]);
+    if (c->stage_done[k]) (void)hipEventDestroy(c->stage_done[k]);
+  }
   if (c->fexp) (void)hipFree(c->fexp);
   if (c->primes) (void)hipFree(c->primes);
-  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
   if (c->batch.exec) (void)hipGraphExecDestroy(c->batch.exec);
   if (c->batch.graph) (void)hipGraphDestroy(c->batch.graph);
   if (c->batch.ws) (void)hipFree(c->batch.ws);

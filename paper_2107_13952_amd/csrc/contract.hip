@@ -154,7 +154,9 @@ hipError_t launch_grad_psi(const ContractParams &cp, double gre, double gim, dou
 namespace {
 
 constexpr int kAdjThreads = 64;  // one wavefront per shell
-constexpr int KD = 16;           // padded matrix dimension
+// The per-shell matrices are padded to KD x KD (KD in 8, 10, 12, 16: the smallest that holds
+// the configuration's dimensions), so that the LDS of a workgroup, and with it the number of
+// workgroups resident per CU, follows the actual dimensions.
 
 struct AdjShell {
   int o[6], t[4], klo[4], kn[4];
@@ -192,6 +194,7 @@ __device__ AdjShell adj_header(const VertexParams &vp, int64_t s) {
 // C(rows x cols) = A(rows x inner) * diag(dg) * B(inner x cols), all in LDS, KD-strided.
 // dg may be null (identity).  Complex A, real or complex B handled by the caller through
 // separate real/imaginary planes: here everything is complex.
+template <int KD>
 __device__ void cmatmul(const cplx *A, const cplx *dg, const cplx *B, cplx *C, int rows, int inner,
                         int cols) {
   for (int idx = threadIdx.x; idx < rows * cols; idx += blockDim.x) {
@@ -206,6 +209,7 @@ __device__ void cmatmul(const cplx *A, const cplx *dg, const cplx *B, cplx *C, i
   }
 }
 
+template <int KD>
 __global__ __launch_bounds__(kAdjThreads) void adjoint_shell_kernel(AdjointParams ap) {
   const VertexParams &vp = ap.v;
   const int64_t s = vp.shell_begin + blockIdx.x;
@@ -275,15 +279,15 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_shell_kernel(AdjointParam
     }
     __syncthreads();
     // Ra = S5 P1 S1 (k2 x k5);  Rb = S2 U4 S3 (k5 x k3)
-    cmatmul(S[4], P1, S[0], Ra, dk[0], n1, dk[3]);
-    cmatmul(S[1], U[2], S[2], Rb, dk[3], dk[2], dk[1]);
+    cmatmul<KD>(S[4], P1, S[0], Ra, dk[0], n1, dk[3]);
+    cmatmul<KD>(S[1], U[2], S[2], Rb, dk[3], dk[2], dk[1]);
     __syncthreads();
     // E = S4 U2 Ra (k3 x k5);  Y = Rb U3 S4 (k5 x k2)
-    cmatmul(S[3], U[0], Ra, E, dk[1], dk[0], dk[3]);
-    cmatmul(Rb, U[1], S[3], Y, dk[3], dk[1], dk[0]);
+    cmatmul<KD>(S[3], U[0], Ra, E, dk[1], dk[0], dk[3]);
+    cmatmul<KD>(Rb, U[1], S[3], Y, dk[3], dk[1], dk[0]);
     __syncthreads();
     // H = E U5 S2 (k3 x k4)
-    cmatmul(E, U[3], S[1], H, dk[1], dk[3], dk[2]);
+    cmatmul<KD>(E, U[3], S[1], H, dk[1], dk[3], dk[2]);
     __syncthreads();
     // Diagonals:
     //  G5(k5) = sum_k3 Rb(k5,k3) U3(k3) E(k3,k5)     G3(k3) = sum_k5 E(k3,k5) U5(k5) Rb(k5,k3)
@@ -359,7 +363,16 @@ __global__ void adjoint_reduce_kernel(AdjointParams ap, double gre, double gim, 
 hipError_t launch_adjoint_shells(const AdjointParams &ap, hipStream_t s) {
   const int64_t n = ap.v.shell_end - ap.v.shell_begin;
   if (n <= 0) return hipSuccess;
-  adjoint_shell_kernel<<<(unsigned)n, kAdjThreads, 0, s>>>(ap);
+  const int d = ap.v.i_n[0] > ap.kpad ? ap.v.i_n[0] : ap.kpad;
+  if (d > 16) return hipErrorInvalidValue;
+  if (d <= 8)
+    adjoint_shell_kernel<8><<<(unsigned)n, kAdjThreads, 0, s>>>(ap);
+  else if (d <= 10)
+    adjoint_shell_kernel<10><<<(unsigned)n, kAdjThreads, 0, s>>>(ap);
+  else if (d <= 12)
+    adjoint_shell_kernel<12><<<(unsigned)n, kAdjThreads, 0, s>>>(ap);
+  else
+    adjoint_shell_kernel<16><<<(unsigned)n, kAdjThreads, 0, s>>>(ap);
   return hipGetLastError();
 }
 
