@@ -16,6 +16,7 @@ Functions mirror the C entry points:
 * ``VertexContract``                                      torch.autograd.Function of F(psi, B)
 """
 import ctypes
+import functools
 import os
 
 import numpy as np
@@ -87,6 +88,13 @@ def _ints(vals, n=None):
 
 def layout(two_j, dl):
     """(dims_i[5], two_ilo[5], booster_offsets int64 array of 4 (dl+1)^3 + 1)."""
+    dims, ilo, offs = _layout(tuple(int(v) for v in two_j), int(dl))
+    return list(dims), list(ilo), offs.copy()
+
+
+@functools.lru_cache(maxsize=64)
+def _layout(two_j, dl):
+    """layout() of a configuration, computed once per process (host-only planning)."""
     dims = (ctypes.c_int * 5)()
     ilo = (ctypes.c_int * 5)()
     offs = np.zeros(4 * (int(dl) + 1) ** 3 + 1, dtype=np.int64)
@@ -94,7 +102,8 @@ def layout(two_j, dl):
                           offs.ctypes.data_as(_i64p))
     if rc:
         raise EprlError(rc, "inadmissible spins or shell count")
-    return list(dims), list(ilo), offs
+    offs.setflags(write=False)
+    return tuple(dims), tuple(ilo), offs
 
 
 def count_terms(two_j, dl):
@@ -184,7 +193,8 @@ def vertex_tensor(two_j, dl, gamma, boosters, out=None):
 
 def vertex_tensor_range(two_j, dl, gamma, boosters, shell_begin, shell_end, accumulate=False, out=None):
     torch = _torch()
-    dims, _, offs = layout(two_j, dl)
+    dims, _, offs = _layout(tuple(int(v) for v in two_j), int(dl))
+    dims = list(dims)
     if boosters.numel() != int(offs[-1]):
         raise ValueError(f"booster buffer holds {boosters.numel()} values, layout needs {int(offs[-1])}")
     bp = _check_dev(boosters, torch.float64, "boosters")

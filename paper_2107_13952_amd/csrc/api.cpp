@@ -50,6 +50,9 @@ struct eprl_ctx {
   // depends on the spins, dl and the workgroup target, and is recomputed when they change).
   std::vector<int> sched_key, sched_bounds;
   int sched_nchunk = 0;
+  // Plan of the last configuration asked for (host data only, keyed by spins and dl).
+  std::vector<int> plan_key;
+  Plan plan_last;
   // Batched path: a dedicated workspace and the instantiated graph of the last batch.
   struct Batch {
     std::vector<int64_t> key;
@@ -194,6 +197,21 @@ int ensure_fexp(eprl_ctx *c, int fact_max) {
   return EPRL_OK;
 }
 
+// The plan of (two_j, dl), made once and kept on the context until another configuration is
+// asked for.  *out stays valid until the next call of plan_for on c.
+int plan_for(eprl_ctx *c, const int two_j[10], int dl, const Plan **out) {
+  std::vector<int> key(two_j, two_j + 10);
+  key.push_back(dl);
+  if (key != c->plan_key) {
+    c->plan_key.clear();
+    int rc = make_plan(two_j, dl, c->plan_last, c->err);
+    if (rc) return rc;
+    c->plan_key = key;
+  }
+  *out = &c->plan_last;
+  return EPRL_OK;
+}
+
 // Device-side state of one configuration: tables built, metadata uploaded.
 // Workgroups per launch of the factorised path: enough for several rounds of resident
 // workgroups on 256 CUs, so that cost-balanced chunks finish together.  A batch uses the same
@@ -212,8 +230,13 @@ struct Prepared {
 // Plan, size the workspace (tables + metadata + `extra` bytes), upload metadata (and `sched`,
 // if given) and build the 6j tables.  `extra` is placed at `prep.tail`.
 int prepare(eprl_ctx *c, const int two_j[10], int dl, size_t extra, Prepared &prep,
-            bool ring_tables = false, const std::vector<int> *sched = nullptr) {
-  int rc = make_plan(two_j, dl, prep.plan, c->err);
+            bool ring_tables = false, const std::vector<int> *sched = nullptr,
+            const Plan *known = nullptr) {
+  int rc = EPRL_OK;
+  if (known)
+    prep.plan = *known;
+  else
+    rc = make_plan(two_j, dl, prep.plan, c->err);
   if (rc) return rc;
   Plan &p = prep.plan;
   if (p.D == 0 || p.kmax > 16)
@@ -328,7 +351,7 @@ int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int acc
   const int nchunk = c->sched_nchunk;
   const size_t pbytes = align_up((size_t)nchunk * probe.a_size * sizeof(double), 256);
   Prepared prep;
-  int rc = prepare(c, two_j, dl, pbytes, prep, true, &bounds);
+  int rc = prepare(c, two_j, dl, pbytes, prep, true, &bounds, &probe);
   if (rc) return rc;
   const Plan &p = prep.plan;
   RingParams rp;
@@ -373,9 +396,10 @@ int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, co
   if (!(gamma > 0.0) || !std::isfinite(gamma))
     return fail(c, EPRL_EINVAL, "gamma must be finite and positive");
   if (!B || !A) return fail(c, EPRL_EINVAL, "null booster or output pointer");
-  Plan probe;
-  int rc = make_plan(two_j, dl, probe, c->err);
+  const Plan *pp = nullptr;
+  int rc = plan_for(c, two_j, dl, &pp);
   if (rc) return rc;
+  const Plan &probe = *pp;
   if (sb < 0 || se > probe.nshell || sb > se)
     return fail(c, EPRL_EINVAL, "shell range outside [0, (dl+1)^6]");
   const int D = probe.D;
@@ -394,7 +418,7 @@ int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, co
   nchunk = (int)((nrange + chunk - 1) / chunk);
   const size_t pbytes = align_up((size_t)nchunk * probe.a_size * sizeof(double), 256);
   Prepared prep;
-  rc = prepare(c, two_j, dl, pbytes, prep);
+  rc = prepare(c, two_j, dl, pbytes, prep, false, nullptr, &probe);
   if (rc) return rc;
   VertexParams vp = vertex_params(prep, B);
   vp.partial = reinterpret_cast<double *>(prep.tail);

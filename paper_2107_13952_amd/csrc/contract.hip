@@ -153,7 +153,7 @@ hipError_t launch_grad_psi(const ContractParams &cp, double gre, double gim, dou
 
 namespace {
 
-constexpr int kAdjThreads = 64;  // one wavefront per shell
+constexpr int kAdjThreads = 128;  // two wavefronts per shell (a 9 x 9 product in one round)
 // The per-shell matrices are padded to KD x KD (KD in 8, 10, 12, 16: the smallest that holds
 // the configuration's dimensions), so that the LDS of a workgroup, and with it the number of
 // workgroups resident per CU, follows the actual dimensions.
