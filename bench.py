@@ -174,8 +174,20 @@ def large_batch(lib, torch, dev):
     t_b = timed(torch, lambda: lib.vertex_tensor_batched(configs, 1.2, bl, outs), 1)
     t_p = timed(torch, lambda: [lib.vertex_tensor(tj, d, 1.2, bb, out=a)
                                 for (tj, d), bb, a in zip(configs, bl, outs)], 1)
+    # Boundary contraction and its adjoint (psi and booster gradients) of every configuration,
+    # with seeded unit complex boundary vectors.
+    psis = [[torch.from_numpy(p).to(dev) for p in workloads.boundary_vectors(
+        workloads.CFG5_SEED * 10 + c, list(a.shape))] for c, a in enumerate(outs)]
+
+    def adjoint_all():
+        for (tj, d), bb, a, ps in zip(configs, bl, outs, psis):
+            lib.contract_boundary(a, ps)
+            lib.contract_boundary_adjoint(tj, d, bb, a, ps, 1.0)
+
+    t_a = timed(torch, adjoint_all, 1)
     return {"workload": "16 seeded configurations, j in 5..7, dl = 6, intertwiner dims 11..14",
-            "terms": terms, "batched_terms_per_s": terms / t_b, "plain_terms_per_s": terms / t_p}
+            "terms": terms, "batched_terms_per_s": terms / t_b, "plain_terms_per_s": terms / t_p,
+            "contraction_and_adjoint_s": t_a}
 
 
 def progress(msg):
