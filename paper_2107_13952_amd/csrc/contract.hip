@@ -153,7 +153,10 @@ hipError_t launch_grad_psi(const ContractParams &cp, double gre, double gim, dou
 
 namespace {
 
-constexpr int kAdjThreads = 128;  // two wavefronts per shell (a 9 x 9 product in one round)
+// Threads per shell: enough for one KD x KD product per round (two wavefronts up to KD = 10,
+// four above).
+template <int KD>
+constexpr int adj_threads() { return KD <= 10 ? 128 : 256; }
 // The per-shell matrices are padded to KD x KD (KD in 8, 10, 12, 16: the smallest that holds
 // the configuration's dimensions), so that the LDS of a workgroup, and with it the number of
 // workgroups resident per CU, follows the actual dimensions.
@@ -210,7 +213,7 @@ __device__ void cmatmul(const cplx *A, const cplx *dg, const cplx *B, cplx *C, i
 }
 
 template <int KD>
-__global__ __launch_bounds__(kAdjThreads) void adjoint_shell_kernel(AdjointParams ap) {
+__global__ __launch_bounds__(adj_threads<KD>()) void adjoint_shell_kernel(AdjointParams ap) {
   const VertexParams &vp = ap.v;
   const int64_t s = vp.shell_begin + blockIdx.x;
   if (s >= vp.shell_end) return;
@@ -366,13 +369,13 @@ hipError_t launch_adjoint_shells(const AdjointParams &ap, hipStream_t s) {
   const int d = ap.v.i_n[0] > ap.kpad ? ap.v.i_n[0] : ap.kpad;
   if (d > 16) return hipErrorInvalidValue;
   if (d <= 8)
-    adjoint_shell_kernel<8><<<(unsigned)n, kAdjThreads, 0, s>>>(ap);
+    adjoint_shell_kernel<8><<<(unsigned)n, adj_threads<8>(), 0, s>>>(ap);
   else if (d <= 10)
-    adjoint_shell_kernel<10><<<(unsigned)n, kAdjThreads, 0, s>>>(ap);
+    adjoint_shell_kernel<10><<<(unsigned)n, adj_threads<10>(), 0, s>>>(ap);
   else if (d <= 12)
-    adjoint_shell_kernel<12><<<(unsigned)n, kAdjThreads, 0, s>>>(ap);
+    adjoint_shell_kernel<12><<<(unsigned)n, adj_threads<12>(), 0, s>>>(ap);
   else
-    adjoint_shell_kernel<16><<<(unsigned)n, kAdjThreads, 0, s>>>(ap);
+    adjoint_shell_kernel<16><<<(unsigned)n, adj_threads<16>(), 0, s>>>(ap);
   return hipGetLastError();
 }
 
