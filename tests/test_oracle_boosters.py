@@ -158,3 +158,30 @@ def test_boosters_real_and_converged():
         pos = offsets[(e - 2) * (dl + 1) ** 3 + t]
         np.testing.assert_allclose(flat[pos:pos + idim * kdim].reshape(idim, kdim), fine.real,
                                    rtol=0, atol=1e-14 * scale)
+
+
+def test_stored_quadrature_boosters_match_the_oracle():
+    """The boosters stored beside the j = 1 golden are the oracle's (recomputed here), and the
+    j = 3 ones have the packed layout's size, are finite and were taken at gamma = 1.2."""
+    import os
+    from oracle import ranges as R
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    g1 = np.load(os.path.join(here, "vertex_j1_dl3_phys.npz"))
+    flat, imag, err = Bo.boosters(list(g1["two_j"]), int(g1["dl"]), float(g1["gamma"]))
+    np.testing.assert_allclose(g1["boosters"], flat, rtol=0, atol=1e-15 * np.abs(flat).max())
+    g3 = np.load(os.path.join(here, "vertex_j3_dl8_phys.npz"))
+    _, offsets = R.booster_layout(list(g3["two_j"]), int(g3["dl"]))
+    assert g3["boosters"].size == offsets[-1]
+    assert np.all(np.isfinite(g3["boosters"])) and float(g3["gamma"]) == 1.2
+    assert int(g3["booster_seed"]) == -1
+
+
+def test_bench_loads_the_stored_quadrature_boosters():
+    import bench
+    from oracle import ranges as R
+    two_j, dl = [6] * 10, 8
+    _, offsets = R.booster_layout(two_j, dl)
+    b = bench.quadrature_boosters(two_j, dl, offsets[-1])
+    assert b is not None and b.dtype == np.float64 and b.size == offsets[-1]
+    assert bench.quadrature_boosters(two_j, dl, offsets[-1] + 1) is None
+    assert bench.quadrature_boosters([8] * 10, dl, offsets[-1]) is None
