@@ -64,7 +64,9 @@ int eprl_create(eprl_ctx **out, int device, void *hip_stream);
 void eprl_destroy(eprl_ctx *ctx);
 /* Text of the last error on this context; valid until the next call on it. */
 const char *eprl_last_error(const eprl_ctx *ctx);
-/* Change the stream subsequent calls are enqueued on. */
+/* Change the stream subsequent calls are enqueued on.  When it differs from the current one,
+ * the new stream is made to wait (an event, no host synchronisation) for the work already
+ * enqueued on the old stream, which may still use the context's workspace. */
 int eprl_set_stream(eprl_ctx *ctx, void *hip_stream);
 
 /* How eprl_vertex_tensor evaluates the shell sum (both give the same tensor up to rounding):

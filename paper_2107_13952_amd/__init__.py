@@ -262,6 +262,10 @@ def contract_boundary_adjoint(two_j, dl, boosters, A, psis, grad_F=1.0, want_psi
     """(g dF/dpsi_a for a = 1..5, g dF/dB) as complex128 device tensors (holomorphic derivatives)."""
     torch = _torch()
     dims, _, offs = layout(two_j, dl)
+    if want_boosters and boosters.numel() != int(offs[-1]):
+        raise ValueError(f"booster buffer holds {boosters.numel()} values, layout needs {int(offs[-1])}")
+    if want_psi and list(A.shape) != dims:
+        raise ValueError(f"vertex tensor shape {list(A.shape)} != {dims}")
     dev = psis[0].device
     g = complex(grad_F)
     gbuf = (ctypes.c_double * 2)(g.real, g.imag)

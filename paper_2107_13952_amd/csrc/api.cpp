@@ -26,6 +26,9 @@ struct eprl_ctx {
   hipEvent_t stage_done[kStages] = {};
   bool stage_pending[kStages] = {};
   int stage_cur = 0;
+  // Recorded on the old stream when the context moves to another one, which then waits for it:
+  // work enqueued earlier still uses the workspace that later calls reuse.
+  hipEvent_t handoff = nullptr;
   // factorial prime-exponent table (device), valid for arguments <= fact_max
   uint16_t *fexp = nullptr;
   int *primes = nullptr;
@@ -170,11 +173,23 @@ int upload(eprl_ctx *c, void *dst, size_t bytes) {
   return EPRL_OK;
 }
 
+// Forgets the instantiated graph of the last batch (it holds device pointers of the context,
+// such as the factorial table, that are about to change).
+void drop_batch_graph(eprl_ctx *c) {
+  if (c->batch.exec) (void)hipGraphExecDestroy(c->batch.exec);
+  if (c->batch.graph) (void)hipGraphDestroy(c->batch.graph);
+  c->batch.exec = nullptr;
+  c->batch.graph = nullptr;
+  c->batch.key.clear();
+}
+
 int ensure_fexp(eprl_ctx *c, int fact_max) {
   if (fact_max <= c->fact_max) return EPRL_OK;
   fact_max = std::max(fact_max, 256);
   std::vector<int> pr = primes_upto(fact_max);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // A captured batch reads the table through its old address: it must be captured again.
+  drop_batch_graph(c);
   if (c->fexp) HIP_TRY(c, hipFree(c->fexp));
   if (c->primes) HIP_TRY(c, hipFree(c->primes));
   c->fexp = nullptr;
@@ -465,13 +480,14 @@ struct BatchEntry {
   size_t tables = 0, boff = 0, kr = 0, sched = 0, partial = 0;  // byte offsets in the workspace
   int nchunk = 0;
   int64_t chunk = 0;
-  std::vector<int> bounds;  // chunk bounds of the factorised path
+  std::vector<int> bounds;      // chunk bounds of the factorised path
+  std::vector<double> ccost;    // estimated cost of each (i1, chunk), in x iterations
 };
 
 int batch_chunks(const Plan &p, bool ring, int target_wg, int &nchunk, int64_t &chunk,
-                 std::vector<int> &bounds) {
+                 std::vector<int> &bounds, std::vector<double> &ccost) {
   if (ring) {
-    nchunk = ring_schedule(p, target_wg > 0 ? target_wg : kRingTargetWG, bounds);
+    nchunk = ring_schedule(p, target_wg > 0 ? target_wg : kRingTargetWG, bounds, &ccost);
     chunk = 0;
   } else {
     const int target_wg = p.D == 8 ? 4096 : 1024;
@@ -541,7 +557,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     if (c->algo == EPRL_ALGO_RING && !b.ring)
       return fail(c, EPRL_ERANGE, "the factorised path does not apply to every configuration");
     batch_chunks(p, b.ring, p.ring_cls >= 0 ? c->tune_wg[p.ring_cls] : 0, b.nchunk, b.chunk,
-                 b.bounds);
+                 b.bounds, b.ccost);
     fact_max = std::max(fact_max, p.fact_max);
     if (b.ring) max_nd = std::max(max_nd, p.nd);
     b.tables = off;
@@ -567,13 +583,16 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   for (int q = 0; q < n; ++q) {
     if (!ent[q].ring) continue;
     ring_index[q] = nring++;
-    double w[5];
-    count_work(ent[q].plan, w);
-    const int cls = ent[q].plan.ring_cls, nrb = ring_row_blocks(cls);
-    const double per = w[3] / ((double)ent[q].nchunk * ent[q].plan.i[0].n * nrb);
-    for (int ch = 0; ch < ent[q].nchunk; ++ch)
-      for (int n1 = 0; n1 < ent[q].plan.i[0].n; ++n1)
-        for (int rb = 0; rb < nrb; ++rb) cls_items[cls].push_back({per, ring_index[q], ch, n1, rb});
+    // Cost of an item: the chunk's x iterations (from the schedule) times the size of the
+    // A(i1) slice, which sets the work of the final contraction of each iteration.
+    const Plan &p = ent[q].plan;
+    const double slice = (double)p.i[1].n * p.i[2].n * p.i[3].n * p.i[4].n;
+    const int cls = p.ring_cls, nrb = ring_row_blocks(cls), nch = ent[q].nchunk;
+    for (int ch = 0; ch < nch; ++ch)
+      for (int n1 = 0; n1 < p.i[0].n; ++n1) {
+        const double cost = ent[q].ccost[(size_t)n1 * nch + ch] * slice;
+        for (int rb = 0; rb < nrb; ++rb) cls_items[cls].push_back({cost, ring_index[q], ch, n1, rb});
+      }
   }
   std::vector<Item> items;
   int cls_begin[9] = {0};
@@ -593,11 +612,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   if (rc) return rc;
   // Drop the previous graph and workspace.
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (c->batch.exec) (void)hipGraphExecDestroy(c->batch.exec);
-  if (c->batch.graph) (void)hipGraphDestroy(c->batch.graph);
-  c->batch.exec = nullptr;
-  c->batch.graph = nullptr;
-  c->batch.key.clear();
+  drop_batch_graph(c);
   if (off > c->batch.ws_size) {
     if (c->batch.ws) (void)hipFree(c->batch.ws);
     c->batch.ws = nullptr;
@@ -771,10 +786,12 @@ int eprl_create(eprl_ctx **out, int device, void *hip_stream) {
   bool ok = hipSetDevice(device) == hipSuccess && ring_init_attributes() == hipSuccess;
   for (int k = 0; ok && k < eprl_ctx::kStages; ++k)
     ok = hipEventCreateWithFlags(&c->stage_done[k], hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&c->handoff, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     for (int k = 0; k < eprl_ctx::kStages; ++k)
       if (c->stage_done[k]) (void)hipEventDestroy(c->stage_done[k]);
+    if (c->handoff) (void)hipEventDestroy(c->handoff);
     delete c;
     return EPRL_EHIP;
   }
@@ -792,6 +809,7 @@ void eprl_destroy(eprl_ctx *c) {
     if (c->stage[k]) (void)hipHostFree(c->stage[k]);
     if (c->stage_done[k]) (void)hipEventDestroy(c->stage_done[k]);
   }
+  if (c->handoff) (void)hipEventDestroy(c->handoff);
   if (c->fexp) (void)hipFree(c->fexp);
   if (c->primes) (void)hipFree(c->primes);
   if (c->batch.exec) (void)hipGraphExecDestroy(c->batch.exec);
@@ -895,7 +913,12 @@ int eprl_autotune(eprl_ctx *c, const int two_j[10], int dl, const double *B, dou
 
 int eprl_set_stream(eprl_ctx *c, void *hip_stream) {
   if (check_ctx(c)) return EPRL_EINVAL;
-  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  if (s == c->stream) return EPRL_OK;
+  // Order the new stream after everything already enqueued on the old one.
+  HIP_TRY(c, hipEventRecord(c->handoff, c->stream));
+  HIP_TRY(c, hipStreamWaitEvent(s, c->handoff, 0));
+  c->stream = s;
   return EPRL_OK;
 }
 

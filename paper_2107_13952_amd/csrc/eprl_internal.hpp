@@ -122,9 +122,11 @@ hipError_t launch_reduce(const ReduceParams &rp, hipStream_t s);
 int ring_class(int DI, int DK, int KW);
 // Splits the cores of the factorised path, for each i1, into chunks of equal estimated cost
 // (x iterations plus the per-core set-up), about target_wg workgroups in all and at most
-// kRingMaxPartialBytes of partial sums; fills bounds ([i1][nchunk + 1]) and returns nchunk.
+// kRingMaxPartialBytes of partial sums; fills bounds ([i1][nchunk + 1]) and, if asked for, the
+// estimated cost of each chunk ([i1][nchunk], in x iterations) and returns nchunk.
 constexpr size_t kRingMaxPartialBytes = size_t(256) << 20;
-int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds);
+int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds,
+                  std::vector<double> *chunk_cost = nullptr);
 int ring_row_blocks(int cls);
 // LDS bytes of the tile class at nd with staging level stg (-1: the most that fits).
 size_t ring_smem_bytes(int cls, int nd, int stg = -1);

@@ -206,7 +206,8 @@ int make_plan(const int two_j[10], int dl, Plan &p, std::string &err) {
   return EPRL_OK;
 }
 
-int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds) {
+int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds,
+                  std::vector<double> *chunk_cost) {
   const int nd = p.nd, nd3 = nd * nd * nd, d1 = p.i[0].n;
   const int ncore = nd * nd3;
   const int nrb = p.ring_cls >= 0 ? ring_row_blocks(p.ring_cls) : 1;
@@ -257,6 +258,7 @@ int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds) {
     }
   }
   bounds.assign((size_t)d1 * (nchunk + 1), 0);
+  if (chunk_cost) chunk_cost->assign((size_t)d1 * nchunk, 0.0);
   for (int n1 = 0; n1 < d1; ++n1) {
     const double *cs = cost.data() + (size_t)n1 * ncore;
     double total = 0.0;
@@ -271,6 +273,9 @@ int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds) {
     }
     bd[0] = 0;
     bd[nchunk] = ncore;
+    if (chunk_cost)
+      for (int ch = 0; ch < nchunk; ++ch)
+        for (int q = bd[ch]; q < bd[ch + 1]; ++q) (*chunk_cost)[(size_t)n1 * nchunk + ch] += cs[q];
   }
   return nchunk;
 }

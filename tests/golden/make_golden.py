@@ -48,6 +48,11 @@ def _registry():
     for c, rows in ((0, [0, 10]), (3, [5, 13])):
         g.update([_batch_entry(f"b5_c{c:02d}_rows", b5, W.CFG5_SEED, c, rows)])
     g.update([_batch_entry("b5_c00_dl2", b5, W.CFG5_SEED, 0, None, dl=2)])
+    # The large-spin configuration with the widest intertwiner ranges (13, 13, 13, 13, 12), on its
+    # first and last i1 rows.
+    g.update([_batch_entry("b5_c05_rows", b5, W.CFG5_SEED, 5, [0, 12])])
+    # A configuration whose 8-wide intertwiner tiles need 32-wide virtual windows (dl = 10).
+    g["cls1_dl10"] = dict(two_j=[1, 3, 6, 2, 11, 9, 1, 7, 9, 10], dl=10, booster_seed=2010, rows=None)
     # Physical boosters: the j = 1, dl = 3 vertex in full and the j = 3, dl = 8 vertex on its
     # first and last i1 rows.
     g["j1_dl3_phys"] = dict(two_j=W.CFG1["two_j"], dl=W.CFG1["dl"], booster_seed=-1, rows=None)

@@ -153,6 +153,24 @@ def test_vertex_tensor_small(lib, torch, algo, two_j, dl, seed):
     assert err <= TOL
 
 
+# Tile classes of the factorised order that the workloads above do not reach: 16-wide boundary
+# tiles with 8-wide virtual tiles (class 4: only i1 above 8), here with and without shells.
+TILE_CLASS_CASES = [([14, 15, 15, 12, 3, 16, 1, 0, 16, 3], 3, 51, 4),
+                    ([14, 8, 13, 11, 12, 8, 2, 5, 7, 6], 0, 52, 4),
+                    ([13, 10, 12, 11, 0, 5, 10, 13, 9, 0], 0, 53, 4)]
+
+
+@pytest.mark.parametrize("two_j,dl,seed,cls", TILE_CLASS_CASES)
+def test_tile_class_against_oracle(lib, torch, algo, two_j, dl, seed, cls):
+    assert lib.count_work(two_j, dl)["ring_class"] == cls
+    b, bd = boosters_for(torch, two_j, dl, seed)
+    note(f"tile class {cls} [{algo}] {two_j} dl={dl}")
+    a = vertex_or_skip(lib, algo, two_j, dl, 1.2, bd).cpu().numpy()
+    err = normwise(a, V.vertex_tensor(two_j, dl, b))
+    note(f"  normwise error {err:.3e}")
+    assert err <= TOL
+
+
 @pytest.mark.parametrize("dl", [0, 2])
 def test_all_spins_zero(lib, torch, algo, dl):
     """Degenerate vertex: all ten spins 0, one intertwiner per node (a 1x1x1x1x1 tensor)."""
@@ -342,7 +360,7 @@ def test_batched_large_spins(lib, torch):
            for c, (tj, dl) in enumerate(configs)]
     note("batched large spins")
     outs = lib.vertex_tensor_batched(configs, 1.2, bds)
-    for name in ("b5_c00_rows", "b5_c03_rows"):
+    for name in ("b5_c00_rows", "b5_c03_rows", "b5_c05_rows"):
         c = int(name[4:6])
         g = load_golden(name, required=False)
         if g is None:
@@ -350,9 +368,25 @@ def test_batched_large_spins(lib, torch):
         err = normwise(outs[c].cpu().numpy()[g["rows"]], g["A"])
         note(f"  {name} normwise error {err:.3e}")
         assert err <= TOL
-    for c in (0, 3, 15):
+    for c in (0, 3, 5, 15):
         tj, dl = configs[c]
         assert torch.equal(outs[c], lib.vertex_tensor(tj, dl, 1.2, bds[c]))
+
+
+def test_batch_graph_survives_factorial_table_growth(lib, torch):
+    """A captured batch reads the context's factorial table; a later call that needs a larger
+    table (6j arguments up to 800) reallocates it, and the next batched call must capture again
+    rather than replay a graph holding the old address."""
+    configs = [(tj, min(dl, 2)) for tj, dl in workloads.cfg3_batch()[:4]]
+    bds = [boosters_for(torch, tj, dl, 3100 + c)[1] for c, (tj, dl) in enumerate(configs)]
+    note("batch graph vs factorial table growth")
+    first = [a.clone() for a in lib.vertex_tensor_batched(configs, 1.2, bds)]
+    big = lib.sixj_batch(np.array([[800, 800, 800, 800, 800, 800]])).cpu().numpy()
+    assert np.isfinite(big).all()
+    again = lib.vertex_tensor_batched(configs, 1.2, bds)
+    torch.cuda.synchronize()
+    for a, r in zip(first, again):
+        assert torch.equal(a, r)
 
 
 @pytest.mark.parametrize("two_j,dl,seed", [([4, 1, 1, 4, 4, 3, 3, 1, 4, 1], 3, 21),

@@ -185,3 +185,40 @@ def test_bench_loads_the_stored_quadrature_boosters():
     assert b is not None and b.dtype == np.float64 and b.size == offsets[-1]
     assert bench.quadrature_boosters(two_j, dl, offsets[-1] + 1) is None
     assert bench.quadrature_boosters([8] * 10, dl, offsets[-1]) is None
+
+
+@pytest.mark.parametrize("jb,lb", [((2, 3, 1, 2), (4, 5, 1, 2)),      # edge-2 shape: three links boosted
+                                   ((3, 2, 4, 1), (3, 4, 6, 3)),
+                                   ((4, 4, 2, 2), (6, 8, 4, 2))])
+def test_block_pairing_against_intertwiner_tensors(jb, lb):
+    """The m-sum of eq. (booster) in ``_block_from_d`` against the same sum written as a tensor
+    contraction of the normalised intertwiners of the spin-network helper (sympy 3jm, written
+    independently of the oracle's 3jm/4jm): with D[m1..m4] = sum_r w(r) prod_a d_a(m_a; r),
+
+        B(i, k) = sum_m iota^j_i[m] iota^l_k[m] D[m] / sqrt((2i+1)(2k+1)).
+
+    A mis-paired magnetic index, a wrong 4jm phase or a swapped pair of links in the oracle's
+    block would change B for these non-zero spins."""
+    from spin_network import intertwiner_stack
+    gamma = 1.2
+    r30, w30, _, _ = Bo._r_nodes(16)
+    wt = w30 * np.sinh(r30) ** 2 / (4 * np.pi)
+    dfun = {}
+    for tj, tl in zip(jb, lb):
+        for tm in range(-tj, tj + 1, 2):
+            dfun[(tj, tl, tm)] = Bo.boost_d(gamma * (tj / 2 + 1), tj, tj, tl, tm, r30)
+    ilo, iota_j = intertwiner_stack(*jb)
+    klo, iota_l = intertwiner_stack(*lb)
+    got = Bo._block_from_d(jb, lb, dfun, wt, (ilo, iota_j.shape[0]), (klo, iota_l.shape[0]))
+    # Magnetic numbers of link a run over -j_a..j_a: the l-side tensor is cut to those m.
+    cut = tuple(slice((tl - tj) // 2, (tl - tj) // 2 + tj + 1) for tj, tl in zip(jb, lb))
+    iota_l = iota_l[(slice(None),) + cut]
+    mats = [np.stack([dfun[(tj, tl, tm)] for tm in range(-tj, tj + 1, 2)]) for tj, tl in zip(jb, lb)]
+    D = np.einsum("ar,br,cr,dr,r->abcd", *mats, wt)
+    ref = np.einsum("ipqrs,kpqrs,pqrs->ik", iota_j, iota_l, D)
+    ref /= np.sqrt(np.outer(ilo + 2 * np.arange(iota_j.shape[0]) + 1.0,
+                            klo + 2 * np.arange(iota_l.shape[0]) + 1.0))
+    assert got.shape == ref.shape
+    scale = np.abs(ref).max()
+    assert scale > 1e-6
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * scale)
