@@ -1,28 +1,32 @@
 """Benchmark of the EPRL vertex-tensor hot path on one MI355X.
 
-One step = one full vertex tensor of the equilateral j = 3 (two_j = 6), dl = 8 workload
-(7^5 FP64 output, 531441 shells of which 498955 live): 6j tables, the shell sum of
-{15j} x booster terms, reduction and normalisation, with the library's default evaluation
-order (the factorised shell sum).  The per-shell order of the paper's framed algorithm is timed
-beside it.  Inputs (seeded synthetic boosters of the right ragged shape) are resident in HBM
-before the timed region.
+One step = the whole hot path over the large-spin batch: 16 seeded irregular 4-simplices with
+spins j in {5, 5.5, 6, 6.5, 7}, dl = 6 (intertwiner dimensions 10..14, 4.9e11 {15j} x booster
+terms), gamma = 1.2: the 16 vertex tensors in one batched call (6j tables, the factorised shell
+sum in one persistent launch, reductions and normalisation, replayed from a captured graph),
+then for every configuration the boundary contraction with five seeded unit complex vectors and
+its adjoint (gradients with respect to the vectors and to every booster entry).  Inputs
+(seeded synthetic boosters of the exact packed shape) are resident in HBM before the timed
+region.
 
 Prints one JSON line:
-  value        {15j} x booster terms per second (terms = sum over live shells of
-               dim(i1) prod_e dim(k_e), independent of the algorithm)
-  roofline     the factorised kernel's useful FP64 rate (exact count of the flops its active
-               index ranges need) against the FP64 matrix peak, with its average duration
-               measured by HIP events on the library's stream
-  cpu_baseline the CPU oracle timed on a bounded sample of the same workload
-  batched      64 seeded irregular configurations (dl 3..10): batched call vs per-config calls
-  differentiation  j=4, dl=8 forward, contraction and adjoint, adjoint vs central differences
-  large_batch  16 seeded large-spin configurations (dl 6): batched vs per-config calls
+  value        {15j} x booster terms of the 16 vertex tensors per second of step
+  roofline     the persistent factorised kernel: its useful FP64 flops (exact count of the
+               multiply-adds its active index ranges need) per launch divided by its average
+               launch duration (HIP events on the library's stream, from a second pass that
+               enqueues the batch's launches directly), against the MI355X FP64 peak
+  cpu_baseline the CPU oracle timed on a bounded sample of the same workload, on every host core
+  batched_vs_plain  forward only: the batched call against 16 plain calls (median of replays)
+  Extra blocks: the equilateral j = 3, dl = 8 plain vertex (``plain_j3_dl8``), the 64-configuration
+  irregular batch (``irregular_batch``) and the j = 4, dl = 8 differentiation check
+  (``differentiation``).
 """
 import argparse
 import hashlib
 import json
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -37,27 +41,53 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 (vector and matrix) peak
 METRIC = "{15j}×booster terms/s (FP64) & FP64-MFMA util; batched vs plain, 1 GPU @1e-10"
 
 
-def cpu_baseline(two_j, dl, boosters_np, nshell_sample):
-    """The oracle on a contiguous block of shells, single thread."""
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _oracle_block(args):
+    """Oracle partial vertex tensor over one block of shells (worker process, one thread)."""
+    two_j, dl, boosters, lo, hi = args
     from threadpoolctl import threadpool_limits
     from oracle import ranges as R
     from oracle import vertex as V
+    with threadpool_limits(limits=1):
+        V.vertex_tensor(two_j, dl, boosters, shells=R.all_shells(dl)[lo:hi])
+    return hi - lo
+
+
+def cpu_baseline(two_j, dl, boosters_np, shells_per_worker):
+    """The oracle on a contiguous block of shells of one configuration, split over a pool of
+    worker processes (one per host core, one thread each)."""
+    from multiprocessing import get_context
+    from oracle import ranges as R
+    # One worker per host core available to this process, at most 16 (the host share of one GPU).
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(16, avail))
     shells = R.all_shells(dl)
     mid = len(shells) // 2
-    block = shells[mid:mid + nshell_sample]
+    n = shells_per_worker * cores
+    block = shells[mid:mid + n]
     n1 = R.boundary_ranges(two_j)[0][1]
     terms = 0.0
     for s in block:
         two_l = R.shell_spins(two_j, s)
         kd = [R.virtual_range(two_l, e)[1] for e in range(2, 6)]
         terms += n1 * float(np.prod(kd))
-    with threadpool_limits(limits=1):
+    jobs = [(two_j, dl, boosters_np, mid + w * shells_per_worker, mid + (w + 1) * shells_per_worker)
+            for w in range(cores)]
+    # Forked before this process touches the GPU (the baseline runs first), so no child ever
+    # holds a GPU context.
+    with get_context("fork").Pool(cores) as pool:
+        pool.map(_oracle_block, jobs[:1])          # import cost outside the timed region
         t0 = time.perf_counter()
-        V.vertex_tensor(two_j, dl, boosters_np, shells=block)
+        pool.map(_oracle_block, jobs)
         dt = time.perf_counter() - t0
-    return {"value": terms / dt, "unit": "terms/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(block)} consecutive shells (from index {mid}) of the same workload, "
-                      f"{terms:.3g} terms in {dt:.1f} s, one thread"}
+    return {"value": terms / dt, "unit": "terms/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} consecutive shells (from index {mid}) of configuration 0 of the batch "
+                      f"(two_j={two_j}, dl={dl}), {terms:.3g} terms in {dt:.1f} s on {cores} "
+                      f"worker processes, one thread each (os.cpu_count() = {os.cpu_count()}, "
+                      f"{avail} in this process's affinity mask)"}
 
 
 def quadrature_boosters(two_j, dl, size):
@@ -72,12 +102,10 @@ def quadrature_boosters(two_j, dl, size):
     return np.ascontiguousarray(g["boosters"], dtype=np.float64)
 
 
-def measured_traffic(split=None):
-    """HBM bytes per ring_kernel launch from the committed counter summary, when it was taken on
-    the current kernel source (same sha256 prefix) with the work split timed here (default:
-    8192 workgroups, all booster blocks staged); otherwise None."""
-    target, stg = (8192, 2) if split is None else (split["target_workgroups"], split["staging_level"])
-    path = os.path.join(ROOT, "profiles", "ring_kernel_j3_dl8_counters.md")
+def measured_traffic(name, key):
+    """HBM bytes per launch of a kernel from a committed counter summary, when it was taken on
+    the current kernel source (same sha256 prefix) and names `key`; otherwise None."""
+    path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2107_13952_amd", "csrc", "ring.hip")
     try:
         text = open(path).read()
@@ -85,38 +113,10 @@ def measured_traffic(split=None):
     except OSError:
         return None
     m = re.search(r"kernel source sha256 ([0-9a-f]{16})", text)
-    t = re.search(r"traffic bytes per launch, split %d %d: ([0-9.eE+]+)" % (target, stg), text)
+    t = re.search(re.escape(key) + r": ([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != digest:
         return None
     return float(t.group(1))
-
-
-def counter_workload(lib, torch, two_j, dl, b, split):
-    """The dominant kernel three times (with the given work split) and a plain 256 MiB device copy
-    three times (the copy calibrates what FETCH_SIZE and WRITE_SIZE read for a known number of
-    bytes)."""
-    cls = lib.count_work(two_j, dl)["ring_class"]
-    lib.set_tuning(cls, split[0], split[1])
-    for _ in range(3):
-        lib.vertex_tensor(two_j, dl, 1.2, b)
-    torch.cuda.synchronize()
-    x = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
-    for _ in range(3):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    print("counter workload done", flush=True)
-
-
-def timed(torch, fn, reps):
-    """Average wall time of fn() over reps calls after one untimed call, synchronised."""
-    fn()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps
 
 
 def block_shapes(lib, two_j, dl):
@@ -125,6 +125,113 @@ def block_shapes(lib, two_j, dl):
     n3 = (dl + 1) ** 3
     return [(dims[e + 1], int((offs[e * n3 + t + 1] - offs[e * n3 + t]) // dims[e + 1]))
             for e in range(4) for t in range(n3)]
+
+
+def event_times(torch, fn, reps, warmup=1):
+    """Per-call durations (ms) of fn() between HIP events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for r in range(reps):
+        fn()
+        ev[r + 1].record()
+    torch.cuda.synchronize()
+    return [ev[r].elapsed_time(ev[r + 1]) for r in range(reps)]
+
+
+def spread(ms):
+    return {"median_ms": statistics.median(ms), "min_ms": min(ms), "max_ms": max(ms), "reps": len(ms)}
+
+
+class LargeBatch:
+    """The 16-configuration large-spin batch with its boundary vectors and output buffers."""
+
+    def __init__(self, lib, torch, dev):
+        self.lib, self.torch = lib, torch
+        self.configs = workloads.cfg5_batch()
+        self.b_np = [workloads.synthetic_boosters(workloads.batch_booster_seed(workloads.CFG5_SEED, c),
+                                                  block_shapes(lib, tj, d))
+                     for c, (tj, d) in enumerate(self.configs)]
+        self.b = [torch.from_numpy(x).to(dev) for x in self.b_np]
+        self.terms = sum(lib.count_terms(tj, d)[1] for tj, d in self.configs)
+        self.outs = [torch.empty(lib.layout(tj, d)[0], dtype=torch.float64, device=dev)
+                     for tj, d in self.configs]
+        self.psis = [[torch.from_numpy(p).to(dev) for p in workloads.boundary_vectors(
+            workloads.CFG5_SEED * 10 + c, lib.layout(tj, d)[0])] for c, (tj, d) in enumerate(self.configs)]
+        self.F = []
+        self.grads = []
+
+    def forward_batched(self):
+        self.lib.vertex_tensor_batched(self.configs, 1.2, self.b, self.outs)
+
+    def forward_plain(self):
+        for (tj, d), bb, a in zip(self.configs, self.b, self.outs):
+            self.lib.vertex_tensor(tj, d, 1.2, bb, out=a)
+
+    def adjoint(self):
+        self.F, self.grads = [], []
+        for (tj, d), bb, a, ps in zip(self.configs, self.b, self.outs, self.psis):
+            self.F.append(self.lib.contract_boundary(a, ps))
+            self.grads.append(self.lib.contract_boundary_adjoint(tj, d, bb, a, ps, 1.0))
+
+    def step(self):
+        self.forward_batched()
+        self.adjoint()
+
+
+def plain_j3(lib, torch, dev, synthetic, autotune, steps):
+    """The equilateral j = 3, dl = 8 vertex, plain calls (the tensor of the paper's Sec. 3.3
+    scaling with all spins equal), with the roofline of its factorised kernel."""
+    cfg = workloads.CFG2
+    two_j, dl = cfg["two_j"], cfg["dl"]
+    dims, _, offs = lib.layout(two_j, dl)
+    b_np = None if synthetic else quadrature_boosters(two_j, dl, int(offs[-1]))
+    physical = b_np is not None
+    if not physical:
+        b_np = workloads.synthetic_boosters(cfg["booster_seed"], block_shapes(lib, two_j, dl))
+    b = torch.from_numpy(b_np).to(dev)
+    out = torch.empty(dims, dtype=torch.float64, device=dev)
+    terms = lib.count_terms(two_j, dl)[1]
+    work = lib.count_work(two_j, dl)
+    tuned = lib.autotune(two_j, dl, b, out) if autotune else None
+    ms = event_times(torch, lambda: lib.vertex_tensor(two_j, dl, 1.2, b, out=out), steps, 3)
+    lib.timing_enable(True)
+    for _ in range(steps):
+        lib.vertex_tensor(two_j, dl, 1.2, b, out=out)
+    torch.cuda.synchronize()
+    kms, kn = lib.timing_read("ring")
+    lib.timing_enable(False)
+    ring_ms = kms / max(kn, 1)
+    med = statistics.median(ms)
+    return {"workload": "plain EPRL vertex tensor, equilateral j=3 (two_j=6), dl=8, 7^5 FP64 tensor, "
+                        + ("quadrature boosters" if physical else "seeded boosters"),
+            "terms": terms, "terms_per_s": terms / (med * 1e-3), "step": spread(ms),
+            "work_split": tuned or "default",
+            "ring_kernel": {"avg_ms": ring_ms, "alg_flops_per_launch": work["ring_useful_flops"],
+                            "achieved_tflops": work["ring_useful_flops"] / (ring_ms * 1e-3) / 1e12,
+                            "frac": work["ring_useful_flops"] / (ring_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                            "mfma_executed_tflops": work["ring_mfma_flops"] / (ring_ms * 1e-3) / 1e12,
+                            "traffic": measured_traffic("ring_kernel_j3_dl8_counters.md",
+                                                        "traffic bytes per launch, split 8192 2")}}
+
+
+def irregular_batch(lib, torch, dev, reps):
+    """64 seeded irregular configurations (j in 1/2..6, dl in 3..10): batched vs plain calls."""
+    configs = workloads.cfg3_batch()
+    bl = [torch.from_numpy(workloads.synthetic_boosters(
+        workloads.batch_booster_seed(workloads.CFG3_SEED, c), block_shapes(lib, tj, d))).to(dev)
+        for c, (tj, d) in enumerate(configs)]
+    terms = sum(lib.count_terms(tj, d)[1] for tj, d in configs)
+    outs = lib.vertex_tensor_batched(configs, 1.2, bl)
+    tb = event_times(torch, lambda: lib.vertex_tensor_batched(configs, 1.2, bl, outs), reps)
+    tp = event_times(torch, lambda: [lib.vertex_tensor(tj, d, 1.2, bb, out=a)
+                                     for (tj, d), bb, a in zip(configs, bl, outs)], reps)
+    return {"workload": "64 seeded configurations, j in 1/2..6, dl in 3..10", "terms": terms,
+            "batched_terms_per_s": terms / (statistics.median(tb) * 1e-3),
+            "plain_terms_per_s": terms / (statistics.median(tp) * 1e-3),
+            "batched": spread(tb), "plain": spread(tp)}
 
 
 def differentiation(lib, torch, dev):
@@ -139,9 +246,10 @@ def differentiation(lib, torch, dev):
     dims, _, offsets = lib.layout(two_j, dl)
     psis = [torch.from_numpy(p).to(dev) for p in workloads.boundary_vectors(cfg["psi_seed"], dims)]
     A = lib.vertex_tensor(two_j, dl, 1.2, b)
-    t_fwd = timed(torch, lambda: lib.vertex_tensor(two_j, dl, 1.2, b, out=A), 3)
-    t_con = timed(torch, lambda: lib.contract_boundary(A, psis), 10)
-    t_adj = timed(torch, lambda: lib.contract_boundary_adjoint(two_j, dl, b, A, psis, 1.0), 2)
+    t_fwd = statistics.median(event_times(torch, lambda: lib.vertex_tensor(two_j, dl, 1.2, b, out=A), 5))
+    t_con = statistics.median(event_times(torch, lambda: lib.contract_boundary(A, psis), 10))
+    t_adj = statistics.median(event_times(
+        torch, lambda: lib.contract_boundary_adjoint(two_j, dl, b, A, psis, 1.0), 5))
     _, gb = lib.contract_boundary_adjoint(two_j, dl, b, A, psis, 1.0)
     gb = gb.cpu().numpy()
     n3 = (dl + 1) ** 3
@@ -158,133 +266,129 @@ def differentiation(lib, torch, dev):
         worst = max(worst, abs(fd - complex(np.dot(gb, d))) / max(abs(fd), abs(fp), abs(fm)))
     terms = lib.count_terms(two_j, dl)[1]
     return {"workload": "equilateral j=4 (two_j=8), dl=8, five seeded unit complex boundary vectors",
-            "forward_ms": t_fwd * 1e3, "forward_terms_per_s": terms / t_fwd,
-            "contract_us": t_con * 1e6, "adjoint_ms": t_adj * 1e3,
+            "forward_ms": t_fwd, "forward_terms_per_s": terms / (t_fwd * 1e-3),
+            "contract_us": t_con * 1e3, "adjoint_ms": t_adj,
             "adjoint_vs_central_difference_max_rel_err": worst}
 
 
-def large_batch(lib, torch, dev):
-    """16 seeded configurations with spins 5..7 and dl = 6: batched graph vs per-configuration calls."""
-    configs = workloads.cfg5_batch()
-    bl = [torch.from_numpy(workloads.synthetic_boosters(
-        workloads.batch_booster_seed(workloads.CFG5_SEED, c), block_shapes(lib, tj, d))).to(dev)
-        for c, (tj, d) in enumerate(configs)]
-    terms = sum(lib.count_terms(tj, d)[1] for tj, d in configs)
-    outs = lib.vertex_tensor_batched(configs, 1.2, bl)
-    t_b = timed(torch, lambda: lib.vertex_tensor_batched(configs, 1.2, bl, outs), 1)
-    t_p = timed(torch, lambda: [lib.vertex_tensor(tj, d, 1.2, bb, out=a)
-                                for (tj, d), bb, a in zip(configs, bl, outs)], 1)
-    # Boundary contraction and its adjoint (psi and booster gradients) of every configuration,
-    # with seeded unit complex boundary vectors.
-    psis = [[torch.from_numpy(p).to(dev) for p in workloads.boundary_vectors(
-        workloads.CFG5_SEED * 10 + c, list(a.shape))] for c, a in enumerate(outs)]
-
-    def adjoint_all():
-        for (tj, d), bb, a, ps in zip(configs, bl, outs, psis):
-            lib.contract_boundary(a, ps)
-            lib.contract_boundary_adjoint(tj, d, bb, a, ps, 1.0)
-
-    t_a = timed(torch, adjoint_all, 1)
-    return {"workload": "16 seeded configurations, j in 5..7, dl = 6, intertwiner dims 11..14",
-            "terms": terms, "batched_terms_per_s": terms / t_b, "plain_terms_per_s": terms / t_p,
-            "contraction_and_adjoint_s": t_a}
-
-
-def progress(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def time_steps(lib, torch, two_j, dl, b, out, steps, warmup, kernel):
-    """Warm up, then time `steps` vertex tensors between two events on the current stream; then
-    the same steps again with the library's per-launch events on, for the kernel breakdown
-    (kept out of the first pass: creating and recording events per launch costs host time)."""
-    for _ in range(warmup):
-        lib.vertex_tensor(two_j, dl, 1.2, b, out=out)
+def counter_workload(lib, torch, dev, which):
+    """The kernel named by `which` three times, then a plain 256 MiB device copy three times (the
+    copy calibrates what FETCH_SIZE and WRITE_SIZE read for a known number of bytes)."""
+    if which == "batch":
+        lb = LargeBatch(lib, torch, dev)
+        for _ in range(3):
+            lb.forward_batched()
+    else:
+        cfg = workloads.CFG2
+        two_j, dl = cfg["two_j"], cfg["dl"]
+        b = torch.from_numpy(workloads.synthetic_boosters(cfg["booster_seed"],
+                                                          block_shapes(lib, two_j, dl))).to(dev)
+        for _ in range(3):
+            lib.vertex_tensor(two_j, dl, 1.2, b)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        lib.vertex_tensor(two_j, dl, 1.2, b, out=out)
-    host_ms = (time.perf_counter() - t0) * 1e3 / steps
-    stop.record()
+    x = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
     torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / steps
-    progress(f"host time per call (enqueue) {host_ms:.3f} ms")
-    lib.timing_enable(True)
-    for _ in range(steps):
-        lib.vertex_tensor(two_j, dl, 1.2, b, out=out)
-    torch.cuda.synchronize()
-    kms, kn = lib.timing_read(kernel)
-    tab_ms, tab_n = lib.timing_read("sixj_tables")
-    red_ms, red_n = lib.timing_read("reduce")
-    lib.timing_enable(False)
-    return ms, kms / max(kn, 1), {"sixj_tables": tab_ms / max(tab_n, 1), kernel: kms / max(kn, 1),
-                                 "reduce": red_ms / max(red_n, 1)}
+    print("counter workload done", flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-shells", type=int, default=3000, help="oracle sample size (0 = skip)")
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-shells", type=int, default=20,
+                    help="oracle shells per host core for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline step (no j=3 plain, irregular batch or j=4 blocks)")
     ap.add_argument("--synthetic-boosters", action="store_true",
-                    help="seeded random boosters instead of the stored quadrature boosters")
-    ap.add_argument("--no-paper-order", action="store_true", help="skip timing the per-shell order")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="time the default work split instead of the autotuned one")
-    ap.add_argument("--no-adjoint", action="store_true", help="skip the j=4 forward/adjoint block")
-    ap.add_argument("--no-large", action="store_true", help="skip the large-spin batch block")
-    ap.add_argument("--counter-workload", action="store_true",
-                    help="run the dominant kernel and a calibration copy for rocprofv3 --pmc, then exit")
-    ap.add_argument("--counter-split", type=int, nargs=2, default=[8192, 2],
-                    metavar=("WORKGROUPS", "STAGING"), help="work split for --counter-workload")
+                    help="seeded boosters for the j=3 block instead of the stored quadrature ones")
+    ap.add_argument("--no-autotune", action="store_true", help="default work split for the j=3 block")
+    ap.add_argument("--counter-workload", choices=["batch", "j3"],
+                    help="run one kernel three times and a calibration copy for rocprofv3 --pmc, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the vertex tensor runs on a single MI355X "
-              "(several GPUs would split the shell sum by ranges of cores); use --gpus 1",
+        print("bench.py measures one GPU: the vertex tensors run on a single MI355X "
+              "(several GPUs would split a batch by configuration, or one vertex by ranges of "
+              "cores, with one sum of the partial tensors at the end); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+
+    cpu = None
+    if args.cpu_shells > 0 and not args.counter_workload:
+        # The oracle's leg runs first, on the host only, before anything initialises the GPU.
+        from oracle import ranges as R
+        tj, d = workloads.cfg5_batch()[0]
+        b0 = workloads.synthetic_boosters(workloads.batch_booster_seed(workloads.CFG5_SEED, 0),
+                                          R.block_shapes(tj, d))
+        progress(f"cpu baseline: oracle on {args.cpu_shells} shells per host core")
+        cpu = cpu_baseline(tj, d, b0, args.cpu_shells)
+        progress(f"cpu baseline: {cpu['value']:.3g} terms/s")
 
     import torch
     import paper_2107_13952_amd as lib
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    cfg = workloads.CFG2
-    two_j, dl = cfg["two_j"], cfg["dl"]
-    dims, ilo, offs = lib.layout(two_j, dl)
-    shapes = [(dims[e + 1], int((offs[e * (dl + 1) ** 3 + t + 1] - offs[e * (dl + 1) ** 3 + t]) // dims[e + 1]))
-              for e in range(4) for t in range((dl + 1) ** 3)]
-    b_np = None if args.synthetic_boosters else quadrature_boosters(two_j, dl, int(offs[-1]))
-    physical = b_np is not None
-    if not physical:
-        b_np = workloads.synthetic_boosters(cfg["booster_seed"], shapes)
-    b = torch.from_numpy(b_np).to(dev)
-    live, terms = lib.count_terms(two_j, dl)
-    work = lib.count_work(two_j, dl)
-    progress(f"workload two_j={two_j} dl={dl}: {live} live shells, {terms:.3g} terms")
-    out = torch.empty(dims, dtype=torch.float64, device=dev)
     if args.counter_workload:
-        counter_workload(lib, torch, two_j, dl, b, args.counter_split)
+        counter_workload(lib, torch, dev, args.counter_workload)
         return
 
+    lb = LargeBatch(lib, torch, dev)
+    works = [lib.count_work(tj, d) for tj, d in lb.configs]
+    useful = sum(w["ring_useful_flops"] for w in works)
+    executed = sum(w["ring_mfma_flops"] for w in works)
+    classes = sorted({w["ring_class"] for w in works})
+    progress(f"large-spin batch: {len(lb.configs)} configurations, {lb.terms:.3g} terms, tile classes {classes}")
     lib.set_algorithm("auto")
-    tuned = None
-    if not args.no_autotune:
-        tuned = lib.autotune(two_j, dl, b, out)
-        progress(f"autotuned: {tuned}")
-    ms, ring_ms, kernels = time_steps(lib, torch, two_j, dl, b, out, args.steps, args.warmup, "ring")
-    progress(f"factorised order: {ms:.3f} ms/step, ring kernel {ring_ms:.3f} ms")
-    useful = work["ring_useful_flops"] / (ring_ms * 1e-3) / 1e12
-    executed = work["ring_mfma_flops"] / (ring_ms * 1e-3) / 1e12
+    lb.forward_batched()                       # capture
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        lb.step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for k in range(args.steps):
+        lb.step()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    ms = ev[0].elapsed_time(ev[-1]) / args.steps
+    progress(f"step {ms:.1f} ms (median {statistics.median(step_ms):.1f})")
+    # Forward only, batched graph vs plain calls.
+    fb = event_times(torch, lb.forward_batched, 5)
+    fp = event_times(torch, lb.forward_plain, 5)
+    fa = event_times(torch, lb.adjoint, 3)
+    progress(f"forward batched {statistics.median(fb):.1f} ms, plain {statistics.median(fp):.1f} ms, "
+             f"contraction + adjoint {statistics.median(fa):.1f} ms")
+    # Second pass with the library's per-launch events on (the batch then enqueues its launches
+    # directly instead of replaying the graph).
+    lib.timing_enable(True)
+    for _ in range(3):
+        lb.forward_batched()
+    torch.cuda.synchronize()
+    kms, kn = lib.timing_read("ring_batch")
+    tab_ms, tab_n = lib.timing_read("sixj_tables")
+    red_ms, red_n = lib.timing_read("reduce")
+    lib.timing_enable(False)
+    lib.timing_enable(True)
+    for _ in range(2):
+        lb.adjoint()
+    torch.cuda.synchronize()
+    adj_ms, adj_n = lib.timing_read("adjoint_shells")
+    lib.timing_enable(False)
+    launches = kn / 3.0
+    kernel_ms = kms / max(kn, 1)
+    alg_per_launch = useful / max(launches, 1.0)
+    achieved = alg_per_launch / (kernel_ms * 1e-3) / 1e12
+    progress(f"ring_batch_kernel {kernel_ms:.2f} ms per launch ({launches:g} launches per step): "
+             f"{achieved:.2f} TFLOP/s useful")
 
     result = {
         "metric": METRIC,
-        "value": terms / (ms * 1e-3),
+        "value": lb.terms / (ms * 1e-3),
         "unit": "terms/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -294,72 +398,43 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": ("synthetic spins; boosters from the FP64 quadrature of eq. (booster) at "
-                 "gamma=1.2 (stored oracle output)" if physical else
-                 "synthetic: seeded N(0,1)/dim(k) boosters of the exact packed shape (A is "
-                 "multilinear in them; the work does not depend on their values)"),
-        "config": {"workload": "plain EPRL vertex tensor, equilateral j=3 (two_j=6), dl=8, "
-                               "gamma=1.2, intertwiners 0..6 (7^5 FP64 tensor)",
-                   "two_j": two_j, "dl": dl, "live_shells": live, "terms": terms,
-                   "algorithm": "factorised shell sum (ring), FP64 matrix-core contractions",
-                   "work_split": tuned or "default"},
-        "roofline": {"bound": "mfma", "achieved": useful, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": useful / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(tuned),
-                     "kernel": "ring_kernel", "avg_ms": ring_ms,
-                     "alg_flops_per_launch": work["ring_useful_flops"],
-                     "alg_flops_per_term": work["ring_useful_flops"] / terms,
-                     "mfma_executed_tflops": executed,
-                     "per_shell_order_flops_over_time_tflops":
-                         work["shell_flops"] / (ring_ms * 1e-3) / 1e12},
-        "kernels_ms": kernels,
+        "data": "synthetic: seeded spins, N(0,1)/dim(k) boosters of the exact packed shape (A is "
+                "multilinear in them; the work does not depend on their values) and unit complex "
+                "Gaussian boundary vectors",
+        "config": {"workload": "large-spin batch: 16 seeded irregular 4-simplices, j in 5..7, dl=6, "
+                               "gamma=1.2, intertwiner dims 10..14; step = batched vertex tensors + "
+                               "boundary contraction and adjoint of each",
+                   "configs": [{"two_j": tj, "dl": d} for tj, d in lb.configs],
+                   "terms": lb.terms, "tile_classes": classes,
+                   "algorithm": "factorised shell sum (ring), FP64 matrix-core contractions, one "
+                                "persistent launch per tile class in a captured graph"},
+        "step_spread": spread(step_ms),
+        "batched_vs_plain": {"forward_batched": spread(fb), "forward_plain": spread(fp),
+                             "batched_terms_per_s": lb.terms / (statistics.median(fb) * 1e-3),
+                             "plain_terms_per_s": lb.terms / (statistics.median(fp) * 1e-3),
+                             "contraction_and_adjoint": spread(fa)},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic("ring_batch_kernel_large_batch_counters.md",
+                                                 "traffic bytes per launch"),
+                     "kernel": "ring_batch_kernel", "avg_ms": kernel_ms,
+                     "launches_per_step": launches,
+                     "alg_flops_per_launch": alg_per_launch,
+                     "alg_flops_per_term": useful / lb.terms,
+                     "mfma_executed_tflops": executed / max(launches, 1.0) / (kernel_ms * 1e-3) / 1e12},
+        "kernels_ms_per_step": {"sixj_tables": tab_ms / 3, "ring_batch": kms / 3, "reduce": red_ms / 3,
+                                "adjoint_shells": adj_ms / 2},
     }
-    if not args.no_paper_order:
-        lib.set_algorithm("shell")
-        steps = max(2, args.steps // 3)
-        pms, asm_ms, pk = time_steps(lib, torch, two_j, dl, b, out, steps, 1, "assemble")
-        lib.set_algorithm("auto")
-        progress(f"per-shell order: {pms:.3f} ms/step, assembly kernel {asm_ms:.3f} ms")
-        result["paper_order"] = {
-            "ms_per_step": pms, "terms_per_s": terms / (pms * 1e-3), "kernels_ms": pk,
-            "kernel_tflops": work["shell_flops"] / (asm_ms * 1e-3) / 1e12,
-            "alg_flops_per_term": work["shell_flops"] / terms}
-    if not args.no_batched:
-        configs = workloads.cfg3_batch()
-        bl = []
-        for c, (tj, d) in enumerate(configs):
-            dd, _, oo = lib.layout(tj, d)
-            sh = [(dd[e + 1], int((oo[e * (d + 1) ** 3 + t + 1] - oo[e * (d + 1) ** 3 + t]) // dd[e + 1]))
-                  for e in range(4) for t in range((d + 1) ** 3)]
-            bl.append(torch.from_numpy(workloads.synthetic_boosters(
-            workloads.batch_booster_seed(workloads.CFG3_SEED, c), sh)).to(dev))
-        bterms = sum(lib.count_terms(tj, d)[1] for tj, d in configs)
-        progress(f"batched workload: {len(configs)} configurations, {bterms:.3g} terms")
-        outs = lib.vertex_tensor_batched(configs, 1.2, bl)
-        torch.cuda.synchronize()
-        progress("batched warm-up done")
-        t0 = time.perf_counter()
-        lib.vertex_tensor_batched(configs, 1.2, bl, outs)
-        torch.cuda.synchronize()
-        t_batched = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        for (tj, d), bb, a in zip(configs, bl, outs):
-            lib.vertex_tensor(tj, d, 1.2, bb, out=a)
-        torch.cuda.synchronize()
-        t_plain = time.perf_counter() - t0
-        progress(f"batched {t_batched:.2f} s, plain {t_plain:.2f} s")
-        result["batched"] = {"workload": "64 seeded configurations, j in 1/2..6, dl in 3..10",
-                             "terms": bterms, "batched_terms_per_s": bterms / t_batched,
-                             "plain_terms_per_s": bterms / t_plain}
-    if not args.no_adjoint:
-        progress("differentiation: j=4 dl=8 forward, contraction, adjoint")
+    if not args.no_extras:
+        progress("plain j=3 dl=8")
+        result["plain_j3_dl8"] = plain_j3(lib, torch, dev, args.synthetic_boosters,
+                                          not args.no_autotune, 10)
+        progress("irregular batch")
+        result["irregular_batch"] = irregular_batch(lib, torch, dev, 5)
+        progress("differentiation j=4 dl=8")
         result["differentiation"] = differentiation(lib, torch, dev)
-    if not args.no_large:
-        progress("large-spin batch: 16 configurations")
-        result["large_batch"] = large_batch(lib, torch, dev)
-    if args.cpu_shells > 0:
-        progress(f"cpu baseline: oracle on {args.cpu_shells} shells")
-        result["cpu_baseline"] = cpu_baseline(two_j, dl, b_np, args.cpu_shells)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 

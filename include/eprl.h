@@ -106,7 +106,9 @@ int eprl_autotune(eprl_ctx *ctx, const int two_j[10], int dl, const double *boos
                   int out[3]);
 
 /* Host-only (no GPU use).  Ranges of the vertex tensor (eq. (vertex-ampl)) and the packed
- * booster layout described above.
+ * booster layout described above.  Every call that plans a configuration returns EPRL_ERANGE
+ * when a 6j symbol of its tables would have an argument above two_j = 200 (j + dl, the
+ * intertwiners and x all at most 100), the range of the device 6j evaluation.
  *   dims_i[5]        out: dim(i1) .. dim(i5)
  *   two_ilo[5]       out (may be NULL): lowest two_i of each boundary intertwiner
  *   booster_offsets  out (may be NULL): 4 (dl+1)^3 + 1 offsets in doubles; the last one is
@@ -140,6 +142,16 @@ int eprl_count_work(const int two_j[10], int dl, double out[5]);
  * The shell sum is evaluated in a fixed order: repeated calls give bitwise identical A. */
 int eprl_vertex_tensor(eprl_ctx *ctx, const int two_j[10], int dl, double gamma,
                        const double *boosters, double *A);
+
+/* The SU(2) BF vertex tensor, the "BF vertex (15j) tensors" of the interface of Sec. 3.2 and
+ * the vertex of the BF studies of Sec. 4.2: eq. (vertex-ampl) with no shells (dl = 0) and no
+ * boosters,
+ *     A(i1..i5) = prod_{e=1..5} sqrt(2 i_e + 1) {15j}(j; i1, i2, i3, i4, i5),
+ * the {15j} of eq. (15j) at l = j and k_e = i_e.  A: device, prod(dims_i) doubles in the
+ * layout of eprl_vertex_tensor ([i1..i5] row-major, dims from eprl_layout with dl = 0),
+ * overwritten.  Any intertwiner dimension is accepted (one thread per entry); spins are
+ * limited only by the 6j range (EPRL_ERANGE above it). */
+int eprl_bf_vertex_tensor(eprl_ctx *ctx, const int two_j[10], double *A);
 
 /* Same, restricted to shells with index in [shell_begin, shell_end) of the (dl+1)^6
  * enumeration.  accumulate = 0 overwrites A, 1 adds to it.  Since A is a sum over shells,
@@ -175,8 +187,9 @@ int eprl_contract_boundary_adjoint(eprl_ctx *ctx, const int two_j[10], int dl,
                                    double *const grad_psi[5], double *grad_boosters);
 
 /* Diagnostic: evaluate n 6j symbols {a b c; d e f} (args: n x 6 two_j values, host int32,
- * each in 0..800)
- * with the same device routine the table builder uses; out: n doubles (device). */
+ * each in 0..200, EPRL_ERANGE otherwise) with the same device routine the table builder uses;
+ * out: n doubles (device).  Up to two_j = 200 the alternating Racah sum cancels by at most
+ * ~1e15, which its double-double evaluation absorbs: results are within a few ulp. */
 int eprl_sixj_batch(eprl_ctx *ctx, int n, const int *args, double *out);
 
 /* Diagnostic: the {15j} tensor W(i1, k2, k3, k4, k5) of one shell (the intermediate of
@@ -187,9 +200,13 @@ int eprl_shell_fifteenj(eprl_ctx *ctx, const int two_j[10], int dl, int64_t shel
 
 /* Per-kernel timing with HIP events recorded on the context's stream around each launch.
  * kernel ids: 0 = 6j table builder, 1 = per-shell vertex assembly, 2 = shell-sum reduction,
- * 3 = adjoint shell kernel, 4 = factorised (ring) vertex assembly.  eprl_timing_enable(ctx, 1)
- * starts recording (clearing earlier records), 0 stops.  eprl_timing_read synchronises the stream and returns the summed
- * duration in milliseconds and the number of launches recorded for `kernel`. */
+ * 3 = adjoint shell kernel, 4 = factorised (ring) vertex assembly, 5 = BF vertex,
+ * 6 = persistent factorised assembly of a batch (one launch per tile class).  While timing is
+ * on, eprl_vertex_tensor_batched enqueues its launch sequence directly instead of replaying
+ * the captured graph (same kernels, same results), so that each launch can be bracketed.
+ * eprl_timing_enable(ctx, 1) starts recording (clearing earlier records), 0 stops.
+ * eprl_timing_read synchronises the stream and returns the summed duration in milliseconds and
+ * the number of launches recorded for `kernel`. */
 int eprl_timing_enable(eprl_ctx *ctx, int enable);
 int eprl_timing_read(eprl_ctx *ctx, int kernel, double *total_ms, int64_t *launches);
 

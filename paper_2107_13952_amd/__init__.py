@@ -9,6 +9,7 @@ Functions mirror the C entry points:
 
 * ``layout(two_j, dl)`` and ``count_terms(two_j, dl)``  (host only)
 * ``vertex_tensor(two_j, dl, gamma, boosters)``          eq. (vertex-ampl)
+* ``bf_vertex_tensor(two_j)``                              the BF (15j) vertex, no boosters
 * ``vertex_tensor_range(...)``                            partial shell sums (resume unit)
 * ``vertex_tensor_batched(configs, gamma, boosters)``     many configurations, one launch
 * ``contract_boundary(A, psis)``                          contraction with five vectors
@@ -47,6 +48,7 @@ _SIGS = {
     "eprl_count_terms": (ctypes.c_int, [_i32p, ctypes.c_int, _i64p, ctypes.POINTER(ctypes.c_double)]),
     "eprl_count_work": (ctypes.c_int, [_i32p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "eprl_vertex_tensor": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_double, _dp, _dp]),
+    "eprl_bf_vertex_tensor": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp]),
     "eprl_vertex_tensor_range": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_double, _dp,
                                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _dp]),
     "eprl_vertex_tensor_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, ctypes.c_double,
@@ -86,6 +88,9 @@ def _ints(vals, n=None):
 
 # ---------------------------------------------------------------- host-only calls
 
+_PLAN_ERRORS = {-4: "a 6j argument of the configuration exceeds two_j = 200 (j + dl, the "
+                    "intertwiners and x must stay within j = 100)"}
+
 def layout(two_j, dl):
     """(dims_i[5], two_ilo[5], booster_offsets int64 array of 4 (dl+1)^3 + 1)."""
     dims, ilo, offs = _layout(tuple(int(v) for v in two_j), int(dl))
@@ -101,7 +106,7 @@ def _layout(two_j, dl):
     rc = _lib.eprl_layout(_ints(two_j, 10), int(dl), dims, ilo,
                           offs.ctypes.data_as(_i64p))
     if rc:
-        raise EprlError(rc, "inadmissible spins or shell count")
+        raise EprlError(rc, _PLAN_ERRORS.get(rc, "inadmissible spins or shell count"))
     offs.setflags(write=False)
     return tuple(dims), tuple(ilo), offs
 
@@ -189,6 +194,20 @@ def _check_dev(t, dtype, name):
 def vertex_tensor(two_j, dl, gamma, boosters, out=None):
     """A[i1, i2, i3, i4, i5] (float64, on the boosters' device), eq. (vertex-ampl)."""
     return vertex_tensor_range(two_j, dl, gamma, boosters, 0, (int(dl) + 1) ** 6, False, out)
+
+
+def bf_vertex_tensor(two_j, device="cuda", out=None):
+    """SU(2) BF vertex prod_e sqrt(2 i_e + 1) {15j}(j; i1..i5) (float64 [i1..i5], no boosters)."""
+    torch = _torch()
+    dims = list(_layout(tuple(int(v) for v in two_j), 0)[0])
+    if out is None:
+        out = torch.empty(dims, dtype=torch.float64, device=device)
+    ap = _check_dev(out, torch.float64, "out")
+    if list(out.shape) != dims:
+        raise ValueError(f"output shape {list(out.shape)} != {dims}")
+    ctx = _ctx(out.device)
+    ctx.check(_lib.eprl_bf_vertex_tensor(ctx.bind(), _ints(two_j, 10), ap))
+    return out
 
 
 def vertex_tensor_range(two_j, dl, gamma, boosters, shell_begin, shell_end, accumulate=False, out=None):
@@ -307,7 +326,8 @@ def shell_fifteenj(two_j, dl, shell, device="cuda"):
     return W[:n].reshape(shape)
 
 
-KERNELS = {"sixj_tables": 0, "assemble": 1, "reduce": 2, "adjoint_shells": 3, "ring": 4}
+KERNELS = {"sixj_tables": 0, "assemble": 1, "reduce": 2, "adjoint_shells": 3, "ring": 4, "bf_vertex": 5,
+           "ring_batch": 6}
 ALGORITHMS = {"auto": 0, "shell": 1, "ring": 2}
 
 

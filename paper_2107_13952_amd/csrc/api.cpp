@@ -10,6 +10,29 @@
 
 using namespace eprl;
 
+// One configuration of a batch: its plan, where its data sits in the batch workspace, and how
+// its shell sum is split.
+struct BatchEntry {
+  Plan plan;
+  bool ring = false;
+  size_t tables = 0, boff = 0, kr = 0, sched = 0, partial = 0;  // byte offsets in the workspace
+  int nchunk = 0;
+  int64_t chunk = 0;
+  std::vector<int> bounds;      // chunk bounds of the factorised path
+  std::vector<double> ccost;    // estimated cost of each (i1, chunk), in x iterations
+};
+
+// The launch sequence of a laid-out batch (host data): replayed from a captured graph, or
+// enqueued directly when per-kernel timing is on.
+struct BatchSeq {
+  std::vector<BatchEntry> ent;
+  std::vector<const double *> B;
+  std::vector<double *> A;
+  int nring = 0, max_nd = 1, ncu = 256;
+  int cls_begin[9] = {0};
+  size_t params_off = 0, items_off = 0, counters_off = 0;
+};
+
 struct eprl_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -64,6 +87,7 @@ struct eprl_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;  // private stream the graph is captured on (default priority)
+    BatchSeq seq;
   } batch;
 };
 
@@ -246,7 +270,7 @@ struct Prepared {
 // if given) and build the 6j tables.  `extra` is placed at `prep.tail`.
 int prepare(eprl_ctx *c, const int two_j[10], int dl, size_t extra, Prepared &prep,
             bool ring_tables = false, const std::vector<int> *sched = nullptr,
-            const Plan *known = nullptr) {
+            const Plan *known = nullptr, bool any_dims = false) {
   int rc = EPRL_OK;
   if (known)
     prep.plan = *known;
@@ -254,7 +278,7 @@ int prepare(eprl_ctx *c, const int two_j[10], int dl, size_t extra, Prepared &pr
     rc = make_plan(two_j, dl, prep.plan, c->err);
   if (rc) return rc;
   Plan &p = prep.plan;
-  if (p.D == 0 || p.kmax > 16)
+  if (!any_dims && (p.D == 0 || p.kmax > 16))
     return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
   rc = ensure_fexp(c, p.fact_max);
   if (rc) return rc;
@@ -474,15 +498,6 @@ int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, co
 // stays the same.  Chunking per configuration equals the single-configuration path, so every
 // tensor is bitwise identical to a separate eprl_vertex_tensor call.
 
-struct BatchEntry {
-  Plan plan;
-  bool ring = false;
-  size_t tables = 0, boff = 0, kr = 0, sched = 0, partial = 0;  // byte offsets in the workspace
-  int nchunk = 0;
-  int64_t chunk = 0;
-  std::vector<int> bounds;      // chunk bounds of the factorised path
-  std::vector<double> ccost;    // estimated cost of each (i1, chunk), in x iterations
-};
 
 int batch_chunks(const Plan &p, bool ring, int target_wg, int &nchunk, int64_t &chunk,
                  std::vector<int> &bounds, std::vector<double> &ccost) {
@@ -518,6 +533,76 @@ TableParams table_params(const Plan &p, double *tables, const eprl_ctx *c) {
   return tp;
 }
 
+// Enqueues the device work of the laid-out batch on c->stream: the 6j tables of every
+// configuration, the work-queue counters (reset by a kernel, so that graph replays start from
+// 0), one persistent ring launch per tile class, per-shell launches for configurations the
+// factorised order does not handle, and the reductions.  Outside a capture each launch is
+// bracketed by the timing events when timing is on.
+hipError_t enqueue_batch(eprl_ctx *c) {
+  const BatchSeq &seq = c->batch.seq;
+  char *ws = c->batch.ws;
+  const int n = (int)seq.ent.size();
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < n && e == hipSuccess; ++q) {
+    const BatchEntry &b = seq.ent[q];
+    TableParams tp = table_params(b.plan, reinterpret_cast<double *>(ws + b.tables), c);
+    TimedLaunch tl(c, 0);
+    e = b.ring ? launch_ring_tables(tp, b.plan.toff[5], c->stream)
+               : launch_sixj_tables(tp, b.plan.toff[5], c->stream);
+  }
+  int *counters = reinterpret_cast<int *>(ws + seq.counters_off);
+  if (e == hipSuccess && seq.nring > 0) e = launch_reset_counters(counters, 8, c->stream);
+  for (int cls = 0; cls < 8 && e == hipSuccess; ++cls) {
+    const int nit = seq.cls_begin[cls + 1] - seq.cls_begin[cls];
+    if (nit == 0) continue;
+    // Enough workgroups to fill the chip at the occupancy the tile class allows.
+    const size_t shm = ring_smem_bytes(cls, seq.max_nd, c->tune_stg[cls]);
+    const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(shm, 1))));
+    const int grid = (int)std::min<int>(nit, seq.ncu * per_cu);
+    TimedLaunch tl(c, 6);
+    e = launch_ring_batch(reinterpret_cast<const RingParams *>(ws + seq.params_off),
+                          reinterpret_cast<const int *>(ws + seq.items_off) + 4 * seq.cls_begin[cls],
+                          nit, cls, seq.max_nd, c->tune_stg[cls], grid, counters + cls, c->stream);
+  }
+  for (int q = 0; q < n && e == hipSuccess; ++q) {
+    const BatchEntry &b = seq.ent[q];
+    if (b.ring) continue;
+    Prepared prep;
+    prep.plan = b.plan;
+    prep.tables = reinterpret_cast<double *>(ws + b.tables);
+    prep.boff = reinterpret_cast<int64_t *>(ws + b.boff);
+    prep.kr = reinterpret_cast<int *>(ws + b.kr);
+    VertexParams vp = vertex_params(prep, seq.B[q]);
+    vp.partial = reinterpret_cast<double *>(ws + b.partial);
+    vp.shell_begin = 0;
+    vp.shell_end = b.plan.nshell;
+    vp.chunk = b.chunk;
+    vp.nchunk = b.nchunk;
+    TimedLaunch tl(c, 1);
+    e = launch_assemble(vp, b.plan.D, c->stream);
+  }
+  for (int q = 0; q < n && e == hipSuccess; ++q) {
+    const BatchEntry &b = seq.ent[q];
+    ReduceParams red = reduce_params(b.plan, reinterpret_cast<double *>(ws + b.partial), b.nchunk,
+                                     seq.A[q], 0);
+    TimedLaunch tl(c, 2);
+    e = launch_reduce(red, c->stream);
+  }
+  return e;
+}
+
+// Runs the current batch: a replay of its graph, or, with per-kernel timing on, the same
+// launch sequence enqueued directly so that every launch can be timed.
+int run_batch(eprl_ctx *c) {
+  if (c->timing) {
+    hipError_t e = enqueue_batch(c);
+    if (e != hipSuccess) return hip_fail(c, e, "batched launch sequence");
+    return EPRL_OK;
+  }
+  HIP_TRY(c, hipGraphLaunch(c->batch.exec, c->stream));
+  return EPRL_OK;
+}
+
 int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
                  const double *const *boosters, double *const *A) {
   std::vector<int64_t> key;
@@ -534,10 +619,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     key.push_back((int64_t)(uintptr_t)A[q]);
     if (!boosters[q] || !A[q]) return fail(c, EPRL_EINVAL, "null booster or output pointer");
   }
-  if (c->batch.exec && key == c->batch.key) {
-    HIP_TRY(c, hipGraphLaunch(c->batch.exec, c->stream));
-    return EPRL_OK;
-  }
+  if (c->batch.exec && key == c->batch.key) return run_batch(c);
   // New batch shape: plan every configuration and lay out the workspace.
   std::vector<BatchEntry> ent(n);
   size_t off = 0;
@@ -698,8 +780,18 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   HIP_TRY(c, hipEventRecord(c->stage_done[c->stage_cur], c->stream));
   c->stage_pending[c->stage_cur] = true;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  int ncu = 256;
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  BatchSeq &seq = c->batch.seq;
+  seq.ent = std::move(ent);
+  seq.B.assign(boosters, boosters + n);
+  seq.A.assign(A, A + n);
+  seq.nring = nring;
+  seq.max_nd = max_nd;
+  std::copy(cls_begin, cls_begin + 9, seq.cls_begin);
+  seq.params_off = params_off;
+  seq.items_off = items_off;
+  seq.counters_off = counters_off;
+  seq.ncu = 256;
+  (void)hipDeviceGetAttribute(&seq.ncu, hipDeviceAttributeMultiprocessorCount, c->device);
   // Capture the device work on a private stream (the caller's stream may be the null stream,
   // which cannot be captured); the graph is then launched on the caller's stream.
   if (!c->batch.cap) HIP_TRY(c, hipStreamCreateWithFlags(&c->batch.cap, hipStreamNonBlocking));
@@ -711,45 +803,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     return hip_fail(c, eb, "hipStreamBeginCapture");
   }
   c->capturing = true;
-  hipError_t e = hipSuccess;
-  for (int q = 0; q < n && e == hipSuccess; ++q) {
-    TableParams tp = table_params(ent[q].plan, reinterpret_cast<double *>(ws + ent[q].tables), c);
-    e = ent[q].ring ? launch_ring_tables(tp, ent[q].plan.toff[5], c->stream)
-                    : launch_sixj_tables(tp, ent[q].plan.toff[5], c->stream);
-  }
-  int *counters = reinterpret_cast<int *>(ws + counters_off);
-  if (e == hipSuccess && nring > 0) e = launch_reset_counters(counters, 8, c->stream);
-  for (int cls = 0; cls < 8 && e == hipSuccess; ++cls) {
-    const int nit = cls_begin[cls + 1] - cls_begin[cls];
-    if (nit == 0) continue;
-    // Enough workgroups to fill the chip at the occupancy the tile class allows.
-    const size_t shm = ring_smem_bytes(cls, max_nd, c->tune_stg[cls]);
-    const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(shm, 1))));
-    const int grid = (int)std::min<int>(nit, ncu * per_cu);
-    e = launch_ring_batch(reinterpret_cast<const RingParams *>(ws + params_off),
-                          reinterpret_cast<const int *>(ws + items_off) + 4 * cls_begin[cls], nit,
-                          cls, max_nd, c->tune_stg[cls], grid, counters + cls, c->stream);
-  }
-  for (int q = 0; q < n && e == hipSuccess; ++q) {
-    if (ent[q].ring) continue;
-    Prepared prep;
-    prep.plan = ent[q].plan;
-    prep.tables = reinterpret_cast<double *>(ws + ent[q].tables);
-    prep.boff = reinterpret_cast<int64_t *>(ws + ent[q].boff);
-    prep.kr = reinterpret_cast<int *>(ws + ent[q].kr);
-    VertexParams vp = vertex_params(prep, boosters[q]);
-    vp.partial = reinterpret_cast<double *>(ws + ent[q].partial);
-    vp.shell_begin = 0;
-    vp.shell_end = ent[q].plan.nshell;
-    vp.chunk = ent[q].chunk;
-    vp.nchunk = ent[q].nchunk;
-    e = launch_assemble(vp, ent[q].plan.D, c->stream);
-  }
-  for (int q = 0; q < n && e == hipSuccess; ++q) {
-    ReduceParams red = reduce_params(ent[q].plan, reinterpret_cast<double *>(ws + ent[q].partial),
-                                     ent[q].nchunk, A[q], 0);
-    e = launch_reduce(red, c->stream);
-  }
+  hipError_t e = enqueue_batch(c);
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
   c->capturing = false;
@@ -768,8 +822,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   c->batch.graph = graph;
   c->batch.exec = exec;
   c->batch.key = key;
-  HIP_TRY(c, hipGraphLaunch(exec, c->stream));
-  return EPRL_OK;
+  return run_batch(c);
 }
 
 }  // namespace
@@ -967,6 +1020,18 @@ int eprl_vertex_tensor(eprl_ctx *c, const int two_j[10], int dl, double gamma, c
   return vertex_range_impl(c, two_j, dl, gamma, B, 0, probe.nshell, 0, A);
 }
 
+int eprl_bf_vertex_tensor(eprl_ctx *c, const int two_j[10], double *A) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!A) return fail(c, EPRL_EINVAL, "null output pointer");
+  Prepared prep;
+  int rc = prepare(c, two_j, 0, 0, prep, false, nullptr, nullptr, true);
+  if (rc) return rc;
+  VertexParams vp = vertex_params(prep, nullptr);
+  TimedLaunch tl(c, 5);
+  HIP_TRY(c, launch_bf_vertex(vp, A, prep.plan.a_size, c->stream));
+  return EPRL_OK;
+}
+
 int eprl_vertex_tensor_range(eprl_ctx *c, const int two_j[10], int dl, double gamma,
                              const double *B, int64_t shell_begin, int64_t shell_end,
                              int accumulate, double *A) {
@@ -1061,7 +1126,8 @@ int eprl_sixj_batch(eprl_ctx *c, int n, const int *args, double *out) {
   if (n == 0) return EPRL_OK;
   int big = 0;
   for (int q = 0; q < 6 * n; ++q) {
-    if (args[q] < 0 || args[q] > 800) return fail(c, EPRL_ERANGE, "6j argument outside 0..800");
+    if (args[q] < 0 || args[q] > kSixjMaxTwo)
+      return fail(c, EPRL_ERANGE, "6j argument outside 0..200 (two_j)");
     big = std::max(big, args[q]);
   }
   int rc = ensure_fexp(c, 2 * big + 2);

@@ -309,7 +309,61 @@ __global__ void shell_fifteenj_kernel(VertexParams vp, int64_t shell, double *W)
   for (int k5 = 0; k5 < dk5; ++k5) W[(int64_t)u * dk5 + k5] = (k5 & 1) ? -s * w[k5] : s * w[k5];
 }
 
+// SU(2) BF vertex (Sec. 3.2 "BF vertex (15j) tensors"; the Delta l = 0, no-booster limit of
+// eq. (vertex-ampl)): A(i1..i5) = prod_e sqrt(2 i_e + 1) {15j}(j; i1..i5).  At dl = 0 every
+// virtual range k_e is the boundary range i_e and the tables hold the 6j symbols of the single
+// shell, so an entry is the x sum of w_row for one k5, with the phase (-1)^R restored in full.
+// One thread per entry: no register tile, so any intertwiner dimension is handled.
+__global__ void bf_vertex_kernel(VertexParams vp, double *A, int64_t total) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= total) return;
+  const ShellHeader h = shell_header(vp, 0);
+  int64_t r = u;
+  const int k5 = (int)(r % h.kn[3]); r /= h.kn[3];
+  const int k4 = (int)(r % h.kn[2]); r /= h.kn[2];
+  const int k3 = (int)(r % h.kn[1]); r /= h.kn[1];
+  const int k2 = (int)(r % h.kn[0]); r /= h.kn[0];
+  const int n1 = (int)r;
+  const int two_i1 = vp.i_lo2[0] + 2 * n1;
+  const int two_k2 = h.klo[0] + 2 * k2, two_k3 = h.klo[1] + 2 * k3, two_k4 = h.klo[2] + 2 * k4;
+  const int two_k5 = h.klo[3] + 2 * k5;
+  const int l24 = h.l[L24], l25 = h.l[L25], l35 = h.l[L35], j13 = h.l[L13], j14 = h.l[L14];
+  // x closes the five triads (i1 l25 x), (k5 j14 x), (l35 k4 x), (l24 k3 x), (j13 k2 x).
+  int lo = imax(imax(iabs(two_i1 - l25), iabs(j13 - two_k2)),
+                imax(imax(iabs(l24 - two_k3), iabs(l35 - two_k4)), iabs(j14 - two_k5)));
+  int hi = imin(imin(two_i1 + l25, j13 + two_k2),
+                imin(imin(l24 + two_k3, l35 + two_k4), j14 + two_k5));
+  lo = imax(lo, vp.X_lo2);
+  hi = imin(hi, vp.X_lo2 + 2 * (vp.NX - 1));
+  const int NX = vp.NX, n_i1 = vp.i_n[0];
+  const int nK2 = vp.K_n[0], nK3 = vp.K_n[1], nK4 = vp.K_n[2], nK5 = vp.K_n[3];
+  const int k2g = (two_k2 - vp.K_lo2[0]) / 2, k3g = (two_k3 - vp.K_lo2[1]) / 2;
+  const int k4g = (two_k4 - vp.K_lo2[2]) / 2, k5g = (two_k5 - vp.K_lo2[3]) / 2;
+  const double *t1 = vp.T1 + ((int64_t)n1 * nK5 + k5g) * NX;
+  const double *t2 = vp.T2 + ((int64_t)k5g * nK4 + k4g) * NX;
+  const double *t3 = vp.T3 + ((int64_t)k4g * nK3 + k3g) * NX;
+  const double *t4 = vp.T4 + ((int64_t)k3g * nK2 + k2g) * NX;
+  const double *t5 = vp.T5 + ((int64_t)k2g * n_i1 + n1) * NX;
+  double w = 0.0;
+  for (int x2 = lo; x2 <= hi; x2 += 2) {
+    const int xg = (x2 - vp.X_lo2) / 2;
+    w += t1[xg] * t2[xg] * t3[xg] * t4[xg] * t5[xg] * (double)(x2 + 1);
+  }
+  // (-1)^R: the header's phase at the lowest intertwiners, one sign per unit step of each.
+  const double sgn = ((n1 + k2 + k3 + k4 + k5) & 1) ? -h.sign : h.sign;
+  double norm = __builtin_sqrt((double)(two_i1 + 1));
+  norm *= __builtin_sqrt((double)(two_k2 + 1)) * __builtin_sqrt((double)(two_k3 + 1));
+  norm *= __builtin_sqrt((double)(two_k4 + 1)) * __builtin_sqrt((double)(two_k5 + 1));
+  A[u] = sgn * w * norm;
+}
+
 }  // namespace
+
+hipError_t launch_bf_vertex(const VertexParams &vp, double *A, int64_t total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  bf_vertex_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(vp, A, total);
+  return hipGetLastError();
+}
 
 hipError_t launch_assemble(const VertexParams &vp, int D, hipStream_t s) {
   if (D == 8) {

@@ -47,6 +47,11 @@ struct Plan {
   int ring_cls = -1;          // tile class of the ring kernel, -1 when it does not apply
 };
 
+// Largest 6j argument (two-units) the device evaluation is built for: up to it the alternating
+// Racah sum cancels by at most ~1e15, which double-double arithmetic absorbs with a few ulp to
+// spare; beyond it the cancellation grows past what 106 bits hold.
+constexpr int kSixjMaxTwo = 200;
+
 // Build a plan; returns EPRL_OK or an error code with a message in `err`.
 int make_plan(const int two_j[10], int dl, Plan &p, std::string &err);
 // Live-shell and term counts (host enumeration).
@@ -141,6 +146,8 @@ hipError_t launch_ring_batch(const RingParams *cfgs_dev, const int *items_dev, i
 hipError_t launch_reset_counters(int *c, int n, hipStream_t s);
 hipError_t launch_shell_fifteenj(const VertexParams &vp, int64_t shell, double *W,
                                  hipStream_t s);
+// BF vertex of a plan made with dl = 0 (tables of the per-shell layout); total = entries of A.
+hipError_t launch_bf_vertex(const VertexParams &vp, double *A, int64_t total, hipStream_t s);
 
 struct ContractParams {
   int n[5];

@@ -72,8 +72,8 @@ int make_plan(const int two_j[10], int dl, Plan &p, std::string &err) {
   // the 6j evaluation below the prime-exponent table limit.
   int maxtwo = 0;
   for (int n = 0; n < 10; ++n) maxtwo = std::max(maxtwo, two_j[n] + 2 * dl);
-  if (maxtwo > 400) {
-    msg << "spin 2j + 2dl = " << maxtwo << " exceeds the supported 400";
+  if (maxtwo > kSixjMaxTwo) {
+    msg << "spin 2j + 2dl = " << maxtwo << " exceeds the supported " << kSixjMaxTwo;
     err = msg.str();
     return EPRL_ERANGE;
   }
@@ -156,6 +156,12 @@ int make_plan(const int two_j[10], int dl, Plan &p, std::string &err) {
   int imax2 = 0;
   for (int e = 0; e < 5; ++e) imax2 = std::max(imax2, p.i[e].lo2 + 2 * (p.i[e].n - 1));
   int big = std::max(std::max(maxtwo, xmax2), std::max(kmax2, imax2));
+  if (big > kSixjMaxTwo) {
+    msg << "a 6j argument of the tables reaches 2j = " << big << ", above the supported "
+        << kSixjMaxTwo;
+    err = msg.str();
+    return EPRL_ERANGE;
+  }
   p.fact_max = 2 * big + 2;
   // 6j table sizes (doubles): T1[nd][n_i1][nK5][NX], T2[nd][nd][nK5][nK4][NX],
   // T3[nd][nd][nd][nK4][nK3][NX], T4[nd][nd][nK3][nK2][NX], T5[nd][nK2][n_i1][NX].

@@ -150,14 +150,22 @@ __device__ double sixj_device(int a, int b, int c, int d, int e, int f, const ui
     else
       den = dde_mul(den, dde_pow(sp, -E));
   }
-  // Series in double-double.
+  // Series in double-double.  Terms can grow far beyond the first one before they fall off:
+  // the running term and sum are scaled down together by 2^-768 (exact) whenever the term
+  // passes 2^768, and the scale is put back at the end.
   dd rho{1.0, 0.0}, sum{1.0, 0.0};
+  int sexp = 0;
   for (int t = tmin; t < tmax; ++t) {
     double nu = -(double)(t + 2) * (double)(be[0] - t) * (double)(be[1] - t) * (double)(be[2] - t);
     double de = (double)(t + 1 - al[0]) * (double)(t + 1 - al[1]) * (double)(t + 1 - al[2]) *
                 (double)(t + 1 - al[3]);
     rho = dd_mul(rho, dd_ratio(nu, de));
     sum = dd_add(sum, rho);
+    if (__builtin_fabs(rho.hi) > 0x1p768) {
+      rho = {__builtin_ldexp(rho.hi, -768), __builtin_ldexp(rho.lo, -768)};
+      sum = {__builtin_ldexp(sum.hi, -768), __builtin_ldexp(sum.lo, -768)};
+      sexp += 768;
+    }
   }
   // value = (-1)^tmin * num / den * sum
   dd q;
@@ -169,7 +177,7 @@ __device__ double sixj_device(int a, int b, int c, int d, int e, int f, const ui
     q = fast_two_sum(qh, diff.hi / den.hi);
   }
   dd v = dd_mul(q, sum);
-  double r = __builtin_ldexp(v.hi + v.lo, num.e - den.e);
+  double r = __builtin_ldexp(v.hi + v.lo, num.e - den.e + sexp);
   return (tmin & 1) ? -r : r;
 }
 

@@ -88,7 +88,13 @@ def test_sixj_device_vs_exact(lib, torch):
         a, b, c, d, e, f = s
         if triad(a, b, c) and triad(a, e, f) and triad(d, b, f) and triad(d, e, c):
             args.append(s)
-    # a few large spins and non-admissible ones
+    # large spins up to the supported two_j = 200 (where the Racah sum cancels most), and
+    # non-admissible ones
+    while len(args) < 3300:
+        s = [rng.randint(100, 200) for _ in range(6)]
+        a, b, c, d, e, f = s
+        if triad(a, b, c) and triad(a, e, f) and triad(d, b, f) and triad(d, e, c):
+            args.append(s)
     args += [[120, 118, 60, 80, 90, 100], [200, 200, 200, 200, 200, 200], [2, 2, 2, 2, 2, 9]]
     note(f"sixj_batch: {len(args)} symbols")
     out = lib.sixj_batch(np.array(args)).cpu().numpy()
@@ -375,14 +381,18 @@ def test_batched_large_spins(lib, torch):
 
 def test_batch_graph_survives_factorial_table_growth(lib, torch):
     """A captured batch reads the context's factorial table; a later call that needs a larger
-    table (6j arguments up to 800) reallocates it, and the next batched call must capture again
+    table (6j arguments up to 200) reallocates it, and the next batched call must capture again
     rather than replay a graph holding the old address."""
     configs = [(tj, min(dl, 2)) for tj, dl in workloads.cfg3_batch()[:4]]
     bds = [boosters_for(torch, tj, dl, 3100 + c)[1] for c, (tj, dl) in enumerate(configs)]
     note("batch graph vs factorial table growth")
     first = [a.clone() for a in lib.vertex_tensor_batched(configs, 1.2, bds)]
-    big = lib.sixj_batch(np.array([[800, 800, 800, 800, 800, 800]])).cpu().numpy()
-    assert np.isfinite(big).all()
+    big = lib.sixj_batch(np.array([[200, 200, 200, 200, 200, 200]])).cpu().numpy()
+    ref = sixj(200, 200, 200, 200, 200, 200)
+    assert abs(big[0] - ref) <= 4 * np.spacing(abs(ref))
+    with pytest.raises(lib.EprlError) as exc:
+        lib.sixj_batch(np.array([[202, 200, 200, 200, 200, 200]]))
+    assert exc.value.code == -4
     again = lib.vertex_tensor_batched(configs, 1.2, bds)
     torch.cuda.synchronize()
     for a, r in zip(first, again):
@@ -558,3 +568,49 @@ def test_adjoint_large_spins(lib, torch):
     note(f"adjoint large spins two_j={tj} dl={dl}")
     _adjoint_full_size(lib, torch, tj, dl, workloads.batch_booster_seed(workloads.CFG5_SEED, 0),
                        workloads.CFG5_SEED, None, [(3, 0)])
+
+
+# ------------------------------------------------------------------ BF vertex (no boosters)
+
+BF_CASES = [[2, 3, 2, 1, 3, 2, 3, 1, 1, 3], [2] * 10, [6] * 10, [0] * 10,
+            [13, 10, 11, 12, 10, 14, 11, 13, 13, 10]]
+
+
+@pytest.mark.parametrize("two_j", BF_CASES)
+def test_bf_vertex_against_oracle(lib, torch, two_j):
+    """The boosterless BF vertex against the oracle's, which is pinned by the brute-force
+    spin network (tests/test_oracle_vertex.py)."""
+    note(f"bf vertex {two_j}")
+    a = lib.bf_vertex_tensor(two_j).cpu().numpy()
+    ref = V.bf_vertex(two_j)
+    assert a.shape == ref.shape
+    err = normwise(a, ref)
+    note(f"  normwise error {err:.3e}")
+    assert err <= TOL
+
+
+def test_bf_vertex_wide_intertwiners(lib, torch):
+    """Intertwiner dimensions above 16 (all spins 10, dimension 21): sampled entries against the
+    oracle's {15j} one by one, and the Delta l = 0 vertex tensor with identity boosters on a case
+    both paths take."""
+    from oracle.fifteenj import fifteenj
+    two_j = [20] * 10
+    note("bf vertex dims 21")
+    a = lib.bf_vertex_tensor(two_j).cpu().numpy()
+    bnd = R.boundary_ranges(two_j)
+    assert a.shape == tuple(n for _, n in bnd)
+    rng = np.random.default_rng(5)
+    idx = [tuple(int(rng.integers(n)) for _, n in bnd) for _ in range(300)]
+    ref = np.array([fifteenj(*[bnd[q][0] + 2 * i[q] for q in range(5)], two_j)
+                    * np.prod([np.sqrt(bnd[q][0] + 2 * i[q] + 1.0) for q in range(5)]) for i in idx])
+    got = np.array([a[i] for i in idx])
+    assert np.abs(got - ref).max() <= TOL * np.abs(a).max()
+    # identity boosters at dl = 0 reproduce the BF vertex through the EPRL path
+    tj = [13, 10, 11, 12, 10, 14, 11, 13, 13, 10]
+    shapes, offsets = R.booster_layout(tj, 0)
+    parts = []
+    for e in range(2, 6):
+        rows, cols, klo = shapes[(e, 0)]
+        parts.append((np.eye(rows) / (klo + 2 * np.arange(cols) + 1.0)[None, :]).ravel())
+    eprl = lib.vertex_tensor(tj, 0, 1.0, torch.from_numpy(np.concatenate(parts)).cuda())
+    assert normwise(eprl.cpu().numpy(), lib.bf_vertex_tensor(tj).cpu().numpy()) <= 1e-13

@@ -85,3 +85,17 @@ def test_factorised_path_limits():
     assert lib.count_work([1] * 10, 15)["ring_class"] >= 0
     assert lib.count_work([1] * 10, 16)["ring_class"] == -1
     assert lib.count_work([6] * 10, 8)["ring_class"] == 0
+
+
+def test_spin_limit_of_the_6j_tables():
+    # Every 6j argument of the tables must stay within two_j = 200, the range of the device
+    # evaluation: the largest virtual spin, and intertwiners and x through the boundary spins.
+    lib = _lib()
+    lib.layout([2] * 10, 97)                                 # x up to i1 + l25 = 4 + 196
+    with pytest.raises(lib.EprlError) as exc:
+        lib.layout([2] * 10, 98)                             # 4 + 198 = 202
+    assert exc.value.code == -4
+    lib.layout([50] * 10, 0)                                 # intertwiners up to 100, x up to 150
+    with pytest.raises(lib.EprlError) as exc:
+        lib.layout([100] * 10, 0)                            # x up to i1 + l25 = 300
+    assert exc.value.code == -4
