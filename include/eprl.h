@@ -175,6 +175,17 @@ int eprl_vertex_tensor_batched(eprl_ctx *ctx, int n, const int *two_j, const int
 int eprl_contract_boundary(eprl_ctx *ctx, const int dims_i[5], const double *A,
                            const double *const psi[5], double *F);
 
+/* Same contraction for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): identical arguments, kernels
+ * and result (bitwise) as eprl_contract_boundary, but the 256 complex partial sums live in a
+ * fixed device array of the library (4 KiB per GPU, held until the process ends) instead of the
+ * context's workspace, and no hipMalloc, hipFree or other allocating call is made.  The array
+ * holds 256 partial sums, which every contraction uses whatever the size of A (EPRL_ERANGE if
+ * a call ever needed more).  All calls on one GPU share the array: calls that overlap in time
+ * on that GPU (different streams or contexts) race and must be ordered by the caller. */
+int eprl_contract_boundary_noalloc(eprl_ctx *ctx, const int dims_i[5], const double *A,
+                                   const double *const psi[5], double *F);
+
 /* Adjoint of the boundary contraction composed with the vertex tensor.  With g = grad_F
  * (host complex), writes g * dF/dpsi_a (device, complex, length dims_i[a]) and
  * g * dF/dB (device, complex, same packing and size as the boosters) where the derivatives

@@ -54,6 +54,7 @@ _SIGS = {
     "eprl_vertex_tensor_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, ctypes.c_double,
                                                   ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
     "eprl_contract_boundary": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp, ctypes.POINTER(ctypes.c_void_p), _dp]),
+    "eprl_contract_boundary_noalloc": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp, ctypes.POINTER(ctypes.c_void_p), _dp]),
     "eprl_contract_boundary_adjoint": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, _dp, _dp,
                                                       ctypes.POINTER(ctypes.c_void_p),
                                                       ctypes.POINTER(ctypes.c_double),
@@ -275,6 +276,22 @@ def contract_boundary(A, psis):
     ctx.check(_lib.eprl_contract_boundary(ctx.bind(), _ints(dims, 5), ap, _psi_ptrs(psis, dims),
                                           ctypes.c_void_p(F.data_ptr())))
     return torch.view_as_complex(F)
+
+
+def contract_boundary_noalloc(A, psis, F):
+    """contract_boundary into a caller-given float64 device tensor F of 2 entries (re, im); the
+    library allocates nothing (its partial sums use a fixed device array)."""
+    torch = _torch()
+    ap = _check_dev(A, torch.float64, "A")
+    fp = _check_dev(F, torch.float64, "F")
+    if F.numel() != 2:
+        raise ValueError("F must hold two float64 values (re, im)")
+    dims = list(A.shape)
+    if len(dims) != 5:
+        raise ValueError("A must have five indices")
+    ctx = _ctx(A.device)
+    ctx.check(_lib.eprl_contract_boundary_noalloc(ctx.bind(), _ints(dims, 5), ap, _psi_ptrs(psis, dims), fp))
+    return F
 
 
 def contract_boundary_adjoint(two_j, dl, boosters, A, psis, grad_F=1.0, want_psi=True, want_boosters=True):

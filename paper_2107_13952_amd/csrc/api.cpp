@@ -49,6 +49,9 @@ struct eprl_ctx {
   hipEvent_t stage_done[kStages] = {};
   bool stage_pending[kStages] = {};
   int stage_cur = 0;
+  // Device address of the contraction's fixed scratch array on this context's device (looked
+  // up once at creation, with the device current).
+  double *scratch = nullptr;
   // Recorded on the old stream when the context moves to another one, which then waits for it:
   // work enqueued earlier still uses the workspace that later calls reuse.
   hipEvent_t handoff = nullptr;
@@ -836,7 +839,8 @@ int eprl_create(eprl_ctx **out, int device, void *hip_stream) {
   if (!c) return EPRL_ENOMEM;
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  bool ok = hipSetDevice(device) == hipSuccess && ring_init_attributes() == hipSuccess;
+  bool ok = hipSetDevice(device) == hipSuccess && ring_init_attributes() == hipSuccess &&
+            contract_scratch_address(&c->scratch) == hipSuccess;
   for (int k = 0; ok && k < eprl_ctx::kStages; ++k)
     ok = hipEventCreateWithFlags(&c->stage_done[k], hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&c->handoff, hipEventDisableTiming) == hipSuccess;
@@ -1065,6 +1069,27 @@ int eprl_contract_boundary(eprl_ctx *c, const int dims_i[5], const double *A,
   int rc = ensure_workspace(c, cp.nblocks * 2 * sizeof(double));
   if (rc) return rc;
   cp.partial = reinterpret_cast<double *>(c->ws);
+  HIP_TRY(c, launch_contract(cp, F, c->stream));
+  return EPRL_OK;
+}
+
+int eprl_contract_boundary_noalloc(eprl_ctx *c, const int dims_i[5], const double *A,
+                                   const double *const psi[5], double *F) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!dims_i || !A || !psi || !F) return fail(c, EPRL_EINVAL, "null argument");
+  if (!c->scratch) return fail(c, EPRL_EHIP, "contraction scratch address unavailable");
+  ContractParams cp;
+  for (int e = 0; e < 5; ++e) {
+    if (dims_i[e] <= 0 || !psi[e]) return fail(c, EPRL_EINVAL, "invalid dimension or vector");
+    cp.n[e] = dims_i[e];
+    cp.psi[e] = psi[e];
+  }
+  cp.A = A;
+  cp.nblocks = 256;
+  if (cp.nblocks > kContractScratchSlots)
+    return fail(c, EPRL_ERANGE, "more partial sums than the fixed scratch holds");
+  // Every block writes its own slot before the final kernel reads it: nothing to clear.
+  cp.partial = c->scratch;
   HIP_TRY(c, launch_contract(cp, F, c->stream));
   return EPRL_OK;
 }

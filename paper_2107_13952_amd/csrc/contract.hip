@@ -126,6 +126,19 @@ __global__ void grad_psi_kernel(ContractParams cp, double gre, double gim, GradP
 
 }  // namespace
 
+// Partial sums of the contraction for callers that cannot allocate: a fixed device array,
+// one copy per GPU, held until the process ends.  Host code never passes its name to a kernel
+// (on the host it is only a stand-in for the symbol); it passes the device address that
+// contract_scratch_address returns for the current device.
+static __device__ __align__(256) double scratch[2 * kContractScratchSlots];
+
+hipError_t contract_scratch_address(double **ptr) {
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  *ptr = e == hipSuccess ? static_cast<double *>(p) : nullptr;
+  return e;
+}
+
 hipError_t launch_contract(const ContractParams &cp, double *F, hipStream_t s) {
   int64_t total = 1;
   for (int e = 0; e < 5; ++e) total *= cp.n[e];

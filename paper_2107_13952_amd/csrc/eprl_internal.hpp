@@ -160,6 +160,10 @@ struct GradPsiOut {
   double *p[5];
 };
 hipError_t launch_contract(const ContractParams &cp, double *F, hipStream_t s);
+// Complex partial-sum slots of the fixed device scratch of the contraction (one per block of
+// contract_partial_kernel) and its device address on the current device.
+constexpr int kContractScratchSlots = 256;
+hipError_t contract_scratch_address(double **ptr);
 hipError_t launch_grad_psi(const ContractParams &cp, double gre, double gim, double *const out[5],
                            hipStream_t s);
 
