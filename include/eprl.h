@@ -78,10 +78,16 @@ int eprl_set_stream(eprl_ctx *ctx, void *hip_stream);
  *                   k3 with FP64 matrix-core tiles.  Needs every i and k range <= 16 and at
  *                   most 16 values per virtual spin (dl <= 15); used for full-range calls
  *                   only (EPRL_ERANGE when forced where it does not apply);
- *  EPRL_ALGO_AUTO   (default) RING where it applies, SHELL otherwise. */
+ *  EPRL_ALGO_AUTO   (default) RING where it applies, SHELL otherwise;
+ *  EPRL_ALGO_RING_VALU  RING restricted to the kernels that take the l45 / l23 half chains on
+ *                   vector ALUs (tile classes 0..7): for boundary dimensions above 8 RING
+ *                   otherwise runs every stage on matrix-core tiles (class 8); kept as a
+ *                   cross-check and for shell counts above 11 (EPRL_ERANGE where neither
+ *                   applies).  Same sum, results agree to rounding. */
 #define EPRL_ALGO_AUTO 0
 #define EPRL_ALGO_SHELL 1
 #define EPRL_ALGO_RING 2
+#define EPRL_ALGO_RING_VALU 3
 int eprl_set_algorithm(eprl_ctx *ctx, int algo);
 
 /* Work split of the factorised order per tile class (the class is out[4] of eprl_count_work):

@@ -345,11 +345,11 @@ def shell_fifteenj(two_j, dl, shell, device="cuda"):
 
 KERNELS = {"sixj_tables": 0, "assemble": 1, "reduce": 2, "adjoint_shells": 3, "ring": 4, "bf_vertex": 5,
            "ring_batch": 6}
-ALGORITHMS = {"auto": 0, "shell": 1, "ring": 2}
+ALGORITHMS = {"auto": 0, "shell": 1, "ring": 2, "ring_valu": 3}
 
 
 def set_algorithm(name, device="cuda"):
-    """Select how vertex tensors are evaluated: "auto" (default), "shell" or "ring"."""
+    """Select how vertex tensors are evaluated: "auto" (default), "shell", "ring" or "ring_valu"."""
     ctx = _ctx(device)
     ctx.check(_lib.eprl_set_algorithm(ctx.handle, ALGORITHMS[name]))
 

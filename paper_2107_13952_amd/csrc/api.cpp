@@ -29,7 +29,7 @@ struct BatchSeq {
   std::vector<const double *> B;
   std::vector<double *> A;
   int nring = 0, max_nd = 1, ncu = 256;
-  int cls_begin[9] = {0};
+  int cls_begin[kRingClasses + 1] = {0};
   size_t params_off = 0, items_off = 0, counters_off = 0;
 };
 
@@ -73,8 +73,8 @@ struct eprl_ctx {
   // Schedule per tile class of the factorised path (set by eprl_autotune or eprl_set_tuning):
   // workgroup target of the cost schedule (0: default) and booster staging level (-1: the
   // most that fits).
-  int tune_wg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int tune_stg[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  int tune_wg[kRingClasses] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int tune_stg[kRingClasses] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
   // Cost schedule of the last configuration run in the factorised order (host data only; it
   // depends on the spins, dl and the workgroup target, and is recomputed when they change).
   std::vector<int> sched_key, sched_bounds;
@@ -385,6 +385,7 @@ int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int acc
   std::vector<int> key(two_j, two_j + 10);
   key.push_back(dl);
   key.push_back(target);
+  key.push_back(cls);
   if (key != c->sched_key) {
     c->sched_nchunk = ring_schedule(probe, target, c->sched_bounds);
     c->sched_key = key;
@@ -421,9 +422,14 @@ int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int acc
   rp.partial = reinterpret_cast<double *>(prep.tail);
   rp.bounds = prep.sched;
   rp.nchunk = nchunk;
+  rp.kw = p.ring_kw;
+  rp.nrb = ring_row_blocks(p);
   {
     TimedLaunch tl(c, 4);
-    HIP_TRY(c, launch_ring(rp, p.ring_cls, c->tune_stg[p.ring_cls], c->stream));
+    if (p.ring_cls == kWideClass)
+      HIP_TRY(c, launch_wide(rp, c->stream));
+    else
+      HIP_TRY(c, launch_ring(rp, p.ring_cls, c->tune_stg[p.ring_cls], c->stream));
   }
   ReduceParams red = reduce_params(p, rp.partial, nchunk, A, accumulate);
   {
@@ -447,12 +453,19 @@ int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, co
   const int D = probe.D;
   if (D == 0) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
   const bool full = sb == 0 && se == probe.nshell;
-  if (c->algo == EPRL_ALGO_RING && (!full || probe.ring_KW == 0))
+  const bool ring_forced = c->algo == EPRL_ALGO_RING || c->algo == EPRL_ALGO_RING_VALU;
+  if (ring_forced && (!full || probe.ring_KW == 0))
     return fail(c, EPRL_ERANGE,
                 "the factorised path needs the full shell range, i and k ranges <= 16 and core "
                 "windows <= 32");
-  if (full && c->algo != EPRL_ALGO_SHELL && probe.ring_KW != 0)
+  if (full && c->algo != EPRL_ALGO_SHELL && probe.ring_KW != 0) {
+    if (c->algo == EPRL_ALGO_RING_VALU && probe.ring_cls != probe.ring_cls8) {
+      Plan q = probe;
+      q.ring_cls = q.ring_cls8;
+      return ring_impl(c, two_j, dl, B, accumulate, A, q);
+    }
     return ring_impl(c, two_j, dl, B, accumulate, A, probe);
+  }
   const int64_t nrange = std::max<int64_t>(se - sb, 1);
   const int target_wg = D == 8 ? 4096 : 1024;
   int nchunk = std::max(1, target_wg / probe.i[0].n);
@@ -554,10 +567,25 @@ hipError_t enqueue_batch(eprl_ctx *c) {
                : launch_sixj_tables(tp, b.plan.toff[5], c->stream);
   }
   int *counters = reinterpret_cast<int *>(ws + seq.counters_off);
-  if (e == hipSuccess && seq.nring > 0) e = launch_reset_counters(counters, 8, c->stream);
-  for (int cls = 0; cls < 8 && e == hipSuccess; ++cls) {
+  if (e == hipSuccess && seq.nring > 0) e = launch_reset_counters(counters, kRingClasses, c->stream);
+  for (int cls = 0; cls < kRingClasses && e == hipSuccess; ++cls) {
     const int nit = seq.cls_begin[cls + 1] - seq.cls_begin[cls];
     if (nit == 0) continue;
+    if (cls == kWideClass) {
+      // One 8-wavefront workgroup per CU, LDS sized for the largest configuration of the class.
+      size_t shm = 0;
+      for (const BatchEntry &b : seq.ent)
+        if (b.ring && b.plan.ring_cls == kWideClass) {
+          int dims[5];
+          for (int q = 0; q < 5; ++q) dims[q] = b.plan.i[q].n;
+          shm = std::max(shm, wide_smem_bytes(b.plan.nd, dims, b.plan.ring_kw, b.plan.ring_nrb));
+        }
+      TimedLaunch tl(c, 6);
+      e = launch_wide_batch(reinterpret_cast<const RingParams *>(ws + seq.params_off),
+                            reinterpret_cast<const int *>(ws + seq.items_off) + 4 * seq.cls_begin[cls],
+                            nit, shm, std::min(nit, seq.ncu), counters + cls, c->stream);
+      continue;
+    }
     // Enough workgroups to fill the chip at the occupancy the tile class allows.
     const size_t shm = ring_smem_bytes(cls, seq.max_nd, c->tune_stg[cls]);
     const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(shm, 1))));
@@ -611,7 +639,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   std::vector<int64_t> key;
   key.push_back(n);
   key.push_back(c->algo);
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < kRingClasses; ++q) {
     key.push_back(c->tune_wg[q]);
     key.push_back(c->tune_stg[q]);
   }
@@ -639,8 +667,9 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     const Plan &p = b.plan;
     if (p.D == 0) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
     b.ring = c->algo != EPRL_ALGO_SHELL && p.ring_KW != 0;
-    if (c->algo == EPRL_ALGO_RING && !b.ring)
+    if ((c->algo == EPRL_ALGO_RING || c->algo == EPRL_ALGO_RING_VALU) && !b.ring)
       return fail(c, EPRL_ERANGE, "the factorised path does not apply to every configuration");
+    if (c->algo == EPRL_ALGO_RING_VALU) b.plan.ring_cls = b.plan.ring_cls8;
     batch_chunks(p, b.ring, p.ring_cls >= 0 ? c->tune_wg[p.ring_cls] : 0, b.nchunk, b.chunk,
                  b.bounds, b.ccost);
     fact_max = std::max(fact_max, p.fact_max);
@@ -662,7 +691,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     double cost;
     int cfg, chunk, n1, rb;
   };
-  std::vector<Item> cls_items[8];
+  std::vector<Item> cls_items[kRingClasses];
   std::vector<int> ring_index(n, -1);
   int nring = 0;
   for (int q = 0; q < n; ++q) {
@@ -672,7 +701,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     // A(i1) slice, which sets the work of the final contraction of each iteration.
     const Plan &p = ent[q].plan;
     const double slice = (double)p.i[1].n * p.i[2].n * p.i[3].n * p.i[4].n;
-    const int cls = p.ring_cls, nrb = ring_row_blocks(cls), nch = ent[q].nchunk;
+    const int cls = p.ring_cls, nrb = ring_row_blocks(p), nch = ent[q].nchunk;
     for (int ch = 0; ch < nch; ++ch)
       for (int n1 = 0; n1 < p.i[0].n; ++n1) {
         const double cost = ent[q].ccost[(size_t)n1 * nch + ch] * slice;
@@ -680,8 +709,8 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
       }
   }
   std::vector<Item> items;
-  int cls_begin[9] = {0};
-  for (int cls = 0; cls < 8; ++cls) {
+  int cls_begin[kRingClasses + 1] = {0};
+  for (int cls = 0; cls < kRingClasses; ++cls) {
     std::stable_sort(cls_items[cls].begin(), cls_items[cls].end(),
                      [](const Item &a, const Item &b) { return a.cost > b.cost; });
     items.insert(items.end(), cls_items[cls].begin(), cls_items[cls].end());
@@ -741,6 +770,8 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     rp.partial = reinterpret_cast<double *>(ws + ent[q].partial);
     rp.bounds = reinterpret_cast<const int *>(ws + ent[q].sched);
     rp.nchunk = ent[q].nchunk;
+    rp.kw = p.ring_kw;
+    rp.nrb = ring_row_blocks(p);
   }
   // Compact staging of the metadata blocks: (workspace offset, bytes) in staging order.
   std::vector<std::pair<size_t, size_t>> blocks;
@@ -789,7 +820,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   seq.A.assign(A, A + n);
   seq.nring = nring;
   seq.max_nd = max_nd;
-  std::copy(cls_begin, cls_begin + 9, seq.cls_begin);
+  std::copy(cls_begin, cls_begin + kRingClasses + 1, seq.cls_begin);
   seq.params_off = params_off;
   seq.items_off = items_off;
   seq.counters_off = counters_off;
@@ -881,7 +912,8 @@ const char *eprl_last_error(const eprl_ctx *c) { return c ? c->err.c_str() : "nu
 
 int eprl_set_algorithm(eprl_ctx *c, int algo) {
   if (check_ctx(c)) return EPRL_EINVAL;
-  if (algo != EPRL_ALGO_AUTO && algo != EPRL_ALGO_SHELL && algo != EPRL_ALGO_RING)
+  if (algo != EPRL_ALGO_AUTO && algo != EPRL_ALGO_SHELL && algo != EPRL_ALGO_RING &&
+      algo != EPRL_ALGO_RING_VALU)
     return fail(c, EPRL_EINVAL, "unknown algorithm");
   c->algo = algo;
   return EPRL_OK;
@@ -889,7 +921,8 @@ int eprl_set_algorithm(eprl_ctx *c, int algo) {
 
 int eprl_set_tuning(eprl_ctx *c, int tile_class, int target_workgroups, int staging_level) {
   if (check_ctx(c)) return EPRL_EINVAL;
-  if (tile_class < 0 || tile_class > 7) return fail(c, EPRL_EINVAL, "tile class outside 0..7");
+  if (tile_class < 0 || tile_class >= kRingClasses)
+    return fail(c, EPRL_EINVAL, "tile class outside 0..8");
   if (target_workgroups != 0 && (target_workgroups < 64 || target_workgroups > (1 << 20)))
     return fail(c, EPRL_EINVAL, "workgroup target must be 0 or in 64..2^20");
   if (staging_level < -1 || staging_level > 2)

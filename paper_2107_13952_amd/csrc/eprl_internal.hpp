@@ -45,6 +45,10 @@ struct Plan {
   int ring_KW = 0;            // 16 or 32 when the ring path applies, else 0
   int ring_DI = 0, ring_DK = 0;  // padded boundary / virtual intertwiner tile sizes (8 or 16)
   int ring_cls = -1;          // tile class of the ring kernel, -1 when it does not apply
+  // Wide (all-matrix-core) kernel, tile class kWideClass: k windows padded to a multiple of 4
+  // and the number of row blocks of A(i1) per work item.
+  int ring_kw = 0, ring_nrb = 1;
+  int ring_cls8 = -1;         // class among 0..7 (half chains on vector ALUs), -1 when none
 };
 
 // Largest 6j argument (two-units) the device evaluation is built for: up to it the alternating
@@ -104,6 +108,7 @@ struct RingParams {
   double *partial;        // [nchunk][i1][i2][i3][i4][i5]
   const int *bounds;      // [i1][nchunk + 1]: first core of each chunk of that i1
   int nchunk;
+  int kw, nrb;            // wide kernel: padded k window, row blocks of A(i1)
 };
 
 struct ReduceParams {
@@ -125,6 +130,21 @@ hipError_t launch_sixj_batch(const int *args, int n, double *out, const uint16_t
 hipError_t launch_assemble(const VertexParams &vp, int D, hipStream_t s);
 hipError_t launch_reduce(const ReduceParams &rp, hipStream_t s);
 int ring_class(int DI, int DK, int KW);
+// Tile classes: 0..7 the 8/16-wide kernels of ring.hip, kWideClass the all-matrix-core kernel of
+// wide.hip (boundary dimensions above 8).
+constexpr int kWideClass = 8;
+constexpr int kRingClasses = 9;
+// Largest dl + 1 the wide kernel takes (its per-spin tiles must fit in LDS beside G and H).
+constexpr int kWideMaxNd = 11;
+size_t wide_smem_bytes(int nd, const int i_n[5], int kw, int nrb);
+// Row blocks of A(i1) per work item so that each wavefront holds at most 12 accumulator tiles
+// (0 when even one row tile needs more).
+int wide_row_blocks(const int i_n[5]);
+bool wide_fits(int nd, const int i_n[5], int kw, int nrb);
+hipError_t wide_init_attributes();
+hipError_t launch_wide(const RingParams &rp, hipStream_t s);
+hipError_t launch_wide_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems,
+                             size_t smem, int grid, int *next, hipStream_t s);
 // Splits the cores of the factorised path, for each i1, into chunks of equal estimated cost
 // (x iterations plus the per-core set-up), about target_wg workgroups in all and at most
 // kRingMaxPartialBytes of partial sums; fills bounds ([i1][nchunk + 1]) and, if asked for, the
@@ -132,7 +152,7 @@ int ring_class(int DI, int DK, int KW);
 constexpr size_t kRingMaxPartialBytes = size_t(256) << 20;
 int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds,
                   std::vector<double> *chunk_cost = nullptr);
-int ring_row_blocks(int cls);
+int ring_row_blocks(const Plan &p);
 // LDS bytes of the tile class at nd with staging level stg (-1: the most that fits).
 size_t ring_smem_bytes(int cls, int nd, int stg = -1);
 // Booster staging levels of the tile class that fit in LDS at nd, most first; returns their count.

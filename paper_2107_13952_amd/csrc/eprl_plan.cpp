@@ -209,6 +209,14 @@ int make_plan(const int two_j[10], int dl, Plan &p, std::string &err) {
   p.ring_KW = w <= 16 ? 16 : (w <= 32 ? 32 : 0);
   if (p.ring_DI == 0 || p.ring_DK == 0 || p.ring_KW == 0 || nd > kRingMaxNd) p.ring_KW = 0;
   p.ring_cls = p.ring_KW ? ring_class(p.ring_DI, p.ring_DK, p.ring_KW) : -1;
+  p.ring_cls8 = p.ring_cls;
+  // Boundary dimensions above 8: the all-matrix-core kernel, when its tiles fit in LDS.
+  int dims[5];
+  for (int e = 0; e < 5; ++e) dims[e] = p.i[e].n;
+  p.ring_kw = (w + 3) / 4 * 4;
+  p.ring_nrb = wide_row_blocks(dims);
+  if (p.ring_cls >= 4 && nd <= kWideMaxNd && wide_fits(nd, dims, p.ring_kw, p.ring_nrb))
+    p.ring_cls = kWideClass;
   return EPRL_OK;
 }
 
@@ -216,7 +224,7 @@ int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds,
                   std::vector<double> *chunk_cost) {
   const int nd = p.nd, nd3 = nd * nd * nd, d1 = p.i[0].n;
   const int ncore = nd * nd3;
-  const int nrb = p.ring_cls >= 0 ? ring_row_blocks(p.ring_cls) : 1;
+  const int nrb = p.ring_cls >= 0 ? ring_row_blocks(p) : 1;
   int nchunk = std::max(1, target_wg / (d1 * nrb));
   nchunk = (int)std::min<int64_t>(nchunk, std::max<int64_t>(1, (int64_t)(kRingMaxPartialBytes / ((size_t)p.a_size * sizeof(double)))));
   nchunk = std::min(nchunk, ncore);
@@ -428,7 +436,31 @@ void count_work(const Plan &p, double out[5]) {
               useful += 2.0 * d5 * d4 * na4 * na3 + 2.0 * d5 * d4 * na3 * d3 * d2;
               const int s4 = ((b4 - w4lo) / 2) / 4 - ((a4 - w4lo) / 2) / 4 + 1;
               const int s3 = ((b3 - w3lo) / 2) / 4 - ((a3 - w3lo) / 2) / 4 + 1;
-              executed += 2.0 * rows * KW * 4 * s4 + 2.0 * rows * cols * 4 * s3;
+              if (p.ring_cls == kWideClass) {
+                // Every stage on 16x16x4 tiles (2048 flops each): T5 / T2 over the active k5 /
+                // k2 values in steps of 4, G / H per active k4 / k3 over the spin values in
+                // steps of 4 (repeated per row block), P over the row tiles and one or two k3
+                // column tiles, the update over all row and column tiles.
+                int tsteps = 0;
+                for (int o = 0; o < nd && o < 64; ++o) {
+                  if (n5[o] > 0) {
+                    const int ka = std::max(lo5[o], std::abs(x - J[L14]));
+                    const int kb = std::min(lo5[o] + 2 * (n5[o] - 1), x + J[L14]);
+                    if (kb >= ka) tsteps += ((kb - lo5[o]) / 2) / 4 - ((ka - lo5[o]) / 2) / 4 + 1;
+                  }
+                  if (n2[o] > 0) {
+                    const int ka = std::max(lo2[o], std::abs(J[L13] - x));
+                    const int kb = std::min(lo2[o] + 2 * (n2[o] - 1), J[L13] + x);
+                    if (kb >= ka) tsteps += ((kb - lo2[o]) / 2) / 4 - ((ka - lo2[o]) / 2) / 4 + 1;
+                  }
+                }
+                const int RT = (d5 * d4 + 15) / 16, CT = (d3 * d2 + 15) / 16;
+                const int nq = ((((b3 - w3lo) / 2) | 3) + 16) / 16;
+                const double per_block = tsteps + (double)(na4 + na3) * ((nd + 3) / 4);
+                executed += 2048.0 * (p.ring_nrb * per_block + (double)RT * nq * s4 + (double)RT * CT * s3);
+              } else {
+                executed += 2.0 * rows * KW * 4 * s4 + 2.0 * rows * cols * 4 * s3;
+              }
             }
           }
         }

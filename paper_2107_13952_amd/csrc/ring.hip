@@ -675,10 +675,14 @@ int ring_class(int DI, int DK, int KW) {
   return (DI == 16 ? 4 : 0) + (DK == 16 ? 2 : 0) + (KW == 32 ? 1 : 0);
 }
 
-int ring_row_blocks(int cls) { return cls >= 4 ? 4 : 1; }
+int ring_row_blocks(const Plan &p) {
+  if (p.ring_cls == kWideClass) return p.ring_nrb;
+  return p.ring_cls >= 4 ? 4 : 1;
+}
 
 size_t ring_smem_bytes(int cls, int nd, int stg) {
   size_t out = 0;
+  if (cls == kWideClass) return 0;  // sized per configuration (wide_smem_bytes)
   dispatch(
       cls, nd,
       [&](auto v) {
@@ -690,6 +694,10 @@ size_t ring_smem_bytes(int cls, int nd, int stg) {
 }
 
 int ring_stage_levels(int cls, int nd, int levels[3]) {
+  if (cls == kWideClass) {  // reads boosters straight into the matrix-core operands
+    levels[0] = 0;
+    return 1;
+  }
   if (cls < 4) {
     levels[0] = 2;
     return 1;
@@ -716,7 +724,7 @@ hipError_t ring_init_attributes() {
     hipError_t e = dispatch(cls, 0, [](auto v) { return decltype(v)::init(); });
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  return wide_init_attributes();
 }
 
 hipError_t launch_ring(const RingParams &rp, int cls, int stg, hipStream_t s) {

@@ -1,0 +1,393 @@
+// Factorised ("ring") evaluation of the vertex tensor for intertwiner dimensions up to 16, with
+// every stage on FP64 matrix-core tiles and the (i5, i4) and (i3, i2) pairs packed densely.
+//
+// The sum regrouped by linearity (eq. (vertex-ampl) with eq. (15j); the same regrouping as the
+// 8-wide kernel of ring.hip, which describes the chain U1 M5 U2 M4 U3 M3 U4 M2 U5): for a fixed
+// i1, core (l24, l25, l34, l35) and x of eq. (15j),
+//   T5(l45; i5, k4) = sum_k5 M5(i5, k5) [U1(k5) U2(k5, k4)]          one 16x16 tile per l45
+//   T2(l23; i2, k3) = sum_k2 M2(i2, k2) [U5(k2) U4(k3, k2)]          one 16x16 tile per l23
+//   G(i5, i4; k4)   = sum_l45 T5(l45; i5, k4) M4(l45; i4, k4)        one 16x16 tile per k4
+//   H(k3; i3, i2)   = sum_l23 M3(l23; i3, k3) T2(l23; i2, k3)        one 16x16 tile per k3
+//   P(rho; k3)      = sum_k4 G(rho; k4) U3(k4, k3)                    rho = i5 d4 + i4
+//   A(i1; rho, sig) += sum_k3 P(rho; k3) H(k3; sig)                   sig = i3 d2 + i2
+// (M_e = (2k_e + 1) B_e, U = signed 6j tables, k4 / k3 over the core's windows).  All six are
+// v_mfma_f64_16x16x4 contractions; the last one, a rank-n3 update of the whole R x C slice
+// (R = d5 d4, C = d3 d2, padded to multiples of 16 only), is where the work is.
+// Lane layout of v_mfma_f64_16x16x4 (lane l = 16 g + c, measured on the device): operand A[c][g],
+// operand B[g][c], result register r = D[g + 4 r][c].
+//
+// One workgroup of 8 wavefronts owns a block of rows of A(i1; rho, sig) (all rows when the
+// slice's tiles fit in 12 accumulator tiles per wavefront, else the rows split into row blocks)
+// for a chunk of cores, and keeps it in MFMA accumulators.  LDS holds the T5/T2 tiles, G (then
+// P, in place) for the block's rows and H; booster entries and 6j values are read from global
+// memory (L1/L2) straight into the MFMA operands.  Stages are separated by workgroup barriers.
+#include "eprl_internal.hpp"
+
+namespace eprl {
+
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int WT = 512;          // threads per workgroup
+constexpr int WW = WT / 64;      // wavefronts per workgroup
+constexpr int kMaxAcc = 12;      // accumulator tiles per wavefront
+constexpr size_t kLdsBytes = 160 * 1024;
+
+__device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
+__device__ __forceinline__ d4v mfma(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// LDS geometry of one configuration (all sizes in doubles).
+struct WideGeom {
+  int R, C, RT, CT, RTb, GS, HS;
+  int t5, t2, g, h, meta;  // offsets
+};
+
+__host__ __device__ inline WideGeom wide_geom(int nd, const int *i_n, int kw, int nrb) {
+  WideGeom w;
+  w.R = i_n[4] * i_n[3];
+  w.C = i_n[2] * i_n[1];
+  w.RT = (w.R + 15) / 16;
+  w.CT = (w.C + 15) / 16;
+  w.RTb = (w.RT + nrb - 1) / nrb;
+  w.GS = kw + 1;
+  w.HS = w.CT * 16 + 1;
+  w.t5 = 0;
+  w.t2 = w.t5 + nd * 256;
+  w.g = w.t2 + nd * 256;
+  w.h = w.g + w.RTb * 16 * w.GS;
+  w.meta = w.h + kw * w.HS;
+  return w;
+}
+
+// Bytes of LDS: the double buffers plus the per-core range table (8 ints per spin value) and
+// booster offsets (4 int64 per spin value).
+__host__ __device__ inline size_t wide_bytes(int nd, const int *i_n, int kw, int nrb) {
+  const WideGeom w = wide_geom(nd, i_n, kw, nrb);
+  return sizeof(double) * (size_t)w.meta + sizeof(int) * 8 * (size_t)nd + sizeof(int64_t) * 4 * (size_t)nd;
+}
+
+// One work item: cores [bounds[i1][chunk], bounds[i1][chunk + 1]) of rp, boundary intertwiner
+// i1 = n1, row block rb of A(i1; rho, sig).
+__device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb, double *smem) {
+  const int nd = rp.nd, nd3 = nd * nd * nd;
+  const int d1 = rp.i_n[0], d2 = rp.i_n[1], d3 = rp.i_n[2], d4 = rp.i_n[3], d5 = rp.i_n[4];
+  const int KW = rp.kw;
+  const WideGeom geo = wide_geom(nd, rp.i_n, KW, rp.nrb);
+  const int rt0 = rb * geo.RTb;
+  const int rtn = imin(geo.RTb, geo.RT - rt0);  // row tiles of this block
+  if (rtn <= 0) return;                          // uniform over the workgroup
+  const int rho0 = rt0 * 16, nrow = rtn * 16;
+  const int ntile = rtn * geo.CT;                // accumulator tiles of the block
+  const int GS = geo.GS, HS = geo.HS, CT = geo.CT;
+  double *T5s = smem + geo.t5;    // [l45][i5][k4 - lo4(l45)]
+  double *T2s = smem + geo.t2;    // [l23][i2][k3 - lo3(l23)]
+  double *Gs = smem + geo.g;      // [rho - rho0][k4 position], then P: [rho - rho0][k3 position]
+  double *Hs = smem + geo.h;      // [k3 position][sig]
+  int *rng = reinterpret_cast<int *>(smem + geo.meta);             // [8][nd]
+  int64_t *bo = reinterpret_cast<int64_t *>(rng + 8 * nd);         // [4][nd]
+
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
+  const int *J = rp.two_j;
+  const int two_i1 = rp.i_lo2[0] + 2 * n1;
+  const int NX = rp.NX, nK2 = rp.K_n[0], nK3 = rp.K_n[1], nK4 = rp.K_n[2], nK5 = rp.K_n[3];
+  const int xhi_g = rp.X_lo2 + 2 * (NX - 1);
+  const double *B = rp.B;
+
+  d4v acc[kMaxAcc];
+#pragma unroll
+  for (int j = 0; j < kMaxAcc; ++j) acc[j] = d4v{0.0, 0.0, 0.0, 0.0};
+  // Rows and columns of G / P and H that the stages never write (padding of the last tile)
+  // must read as zeros.
+  for (int q = tid; q < nrow * GS; q += WT) Gs[q] = 0.0;
+  for (int q = tid; q < KW * HS; q += WT) Hs[q] = 0.0;
+
+  const int c0 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index];
+  const int c1 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index + 1];
+  for (int core = c0; core < c1; ++core) {
+    const int o24 = core / nd3, o25 = (core / (nd * nd)) % nd, o34 = (core / nd) % nd, o35 = core % nd;
+    const int l24 = J[L24] + 2 * o24, l25 = J[L25] + 2 * o25, l35 = J[L35] + 2 * o35;
+    __syncthreads();  // previous readers of rng / bo (and of the LDS tiles) are done
+    for (int o = tid; o < nd; o += WT) {
+      const int t5 = (o25 * nd + o35) * nd + o, t4 = (o * nd + o24) * nd + o34;
+      const int t2 = (o * nd + o24) * nd + o25, t3 = (o34 * nd + o35) * nd + o;
+      int n5 = rp.kr[(3 * nd3 + t5) * 2 + 1], n4 = rp.kr[(2 * nd3 + t4) * 2 + 1];
+      int n2 = rp.kr[(0 * nd3 + t2) * 2 + 1], n3 = rp.kr[(1 * nd3 + t3) * 2 + 1];
+      // A spin whose pair of ranges has an empty member does not contribute.
+      if (n5 == 0 || n4 == 0) n5 = n4 = 0;
+      if (n2 == 0 || n3 == 0) n2 = n3 = 0;
+      rng[0 * nd + o] = rp.kr[(3 * nd3 + t5) * 2];
+      rng[1 * nd + o] = n5;
+      rng[2 * nd + o] = rp.kr[(2 * nd3 + t4) * 2];
+      rng[3 * nd + o] = n4;
+      rng[4 * nd + o] = rp.kr[(0 * nd3 + t2) * 2];
+      rng[5 * nd + o] = n2;
+      rng[6 * nd + o] = rp.kr[(1 * nd3 + t3) * 2];
+      rng[7 * nd + o] = n3;
+      bo[0 * nd + o] = rp.boff[3 * nd3 + t5];  // M5
+      bo[1 * nd + o] = rp.boff[2 * nd3 + t4];  // M4
+      bo[2 * nd + o] = rp.boff[0 * nd3 + t2];  // M2
+      bo[3 * nd + o] = rp.boff[1 * nd3 + t3];  // M3
+    }
+    __syncthreads();
+    // Core windows of k4 (over l45) and of k3 (over l23).
+    int w4lo = 1 << 30, w4hi = -1, w3lo = 1 << 30, w3hi = -1;
+    for (int o = 0; o < nd; ++o) {
+      if (rng[3 * nd + o] > 0) {
+        w4lo = imin(w4lo, rng[2 * nd + o]);
+        w4hi = imax(w4hi, rng[2 * nd + o] + 2 * (rng[3 * nd + o] - 1));
+      }
+      if (rng[7 * nd + o] > 0) {
+        w3lo = imin(w3lo, rng[6 * nd + o]);
+        w3hi = imax(w3hi, rng[6 * nd + o] + 2 * (rng[7 * nd + o] - 1));
+      }
+    }
+    if (w4hi < 0 || w3hi < 0) continue;  // uniform: no live shell in this core
+    const int xlo = imax(iabs(two_i1 - l25), rp.X_lo2), xhi = imin(two_i1 + l25, xhi_g);
+    const int64_t u3base = (((int64_t)o24 * nd + o34) * nd + o35) * NX;
+    auto windows = [&](int x, int &a4, int &b4, int &a3, int &b3) {
+      a4 = imax(w4lo, iabs(l35 - x));
+      b4 = imin(w4hi, l35 + x);
+      a3 = imax(w3lo, iabs(l24 - x));
+      b3 = imin(w3hi, l24 + x);
+      return a4 <= b4 && a3 <= b3;
+    };
+    for (int x = xlo; x <= xhi; x += 2) {
+      int a4, b4, a3, b3;
+      if (!windows(x, a4, b4, a3, b3)) continue;  // uniform
+      const int a4l = (a4 - w4lo) / 2, b4l = (b4 - w4lo) / 2;
+      const int a3l = (a3 - w3lo) / 2, b3l = (b3 - w3lo) / 2;
+      const int xg = (x - rp.X_lo2) / 2;
+      __syncthreads();  // previous x's readers of T5s / T2s / Gs / Hs are done
+
+      // ---- T5 (per l45) and T2 (per l23): 16x16 tiles, K over the k5 (k2) values active at x.
+      for (int u = w; u < 2 * nd; u += WW) {
+        const int o = u < nd ? u : u - nd;
+        d4v t = d4v{0.0, 0.0, 0.0, 0.0};
+        if (u < nd) {
+          const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
+          const int ka = imax(lo5, iabs(x - J[L14])), kb = imin(lo5 + 2 * (n5 - 1), x + J[L14]);
+          const int ia = (ka - lo5) >> 1, ib = (kb - lo5) >> 1;  // empty when kb < ka
+          const int64_t bm = bo[0 * nd + o];
+          const int k4g = (lo4 + 2 * c - rp.K_lo2[2]) >> 1;
+          const double *u1 = rp.U1 + (((int64_t)o25 * NX + xg) * d1 + n1) * nK5;
+          const double *u2 = rp.U2 + (((int64_t)o35 * nd + o) * NX + xg) * nK5 * nK4 + k4g;
+          for (int kk = ia & ~3; kb >= ka && kk <= ib; kk += 4) {
+            const int ki = kk + g;
+            const bool kin = ki >= ia && ki <= ib;
+            const int k5 = lo5 + 2 * ki, k5g = (k5 - rp.K_lo2[3]) >> 1;
+            const double a = (kin && c < d5) ? B[bm + (int64_t)c * n5 + ki] * (double)(k5 + 1) : 0.0;
+            const double b = (kin && c < n4) ? u1[k5g] * u2[(int64_t)k5g * nK4] : 0.0;
+            t = mfma(a, b, t);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) T5s[(o * 16 + g + 4 * r) * 16 + c] = t[r];
+        } else {
+          const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
+          const int ka = imax(lo2, iabs(J[L13] - x)), kb = imin(lo2 + 2 * (n2 - 1), J[L13] + x);
+          const int ia = (ka - lo2) >> 1, ib = (kb - lo2) >> 1;
+          const int64_t bm = bo[2 * nd + o];
+          const int k3g = (lo3 + 2 * c - rp.K_lo2[1]) >> 1;
+          const double *u5 = rp.U5 + ((int64_t)o25 * NX + xg) * nK2 * d1 + n1;
+          const double *u4 = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g) * nK2;
+          for (int kk = ia & ~3; kb >= ka && kk <= ib; kk += 4) {
+            const int ki = kk + g;
+            const bool kin = ki >= ia && ki <= ib;
+            const int k2 = lo2 + 2 * ki, k2g = (k2 - rp.K_lo2[0]) >> 1;
+            const double a = (kin && c < d2) ? B[bm + (int64_t)c * n2 + ki] * (double)(k2 + 1) : 0.0;
+            const double b = (kin && c < n3) ? u5[(int64_t)k2g * d1] * u4[k2g] : 0.0;
+            t = mfma(a, b, t);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) T2s[(o * 16 + g + 4 * r) * 16 + c] = t[r];
+        }
+      }
+      __syncthreads();
+
+      // ---- G (per k4 position) and H (per k3 position): 16x16 tiles, K over l45 (l23).
+      const int g0 = a4l & ~3, nG = (b4l | 3) - g0 + 1;
+      const int h0 = a3l & ~3, nH = (b3l | 3) - h0 + 1;
+      for (int u = w; u < nG + nH; u += WW) {
+        if (u < nG) {
+          const int p = g0 + u, k4 = w4lo + 2 * p;
+          d4v t = d4v{0.0, 0.0, 0.0, 0.0};
+          if (p >= a4l && p <= b4l) {
+            for (int kk = 0; kk < nd; kk += 4) {
+              const int o = kk + g;
+              bool ok = false;
+              int k4i = 0, n4 = 0;
+              if (o < nd) {
+                const int lo4 = rng[2 * nd + o];
+                n4 = rng[3 * nd + o];
+                k4i = (k4 - lo4) >> 1;
+                ok = n4 > 0 && k4 >= lo4 && k4i < n4;
+              }
+              const double a = ok ? T5s[(o * 16 + c) * 16 + k4i] : 0.0;
+              const double b = (ok && c < d4) ? B[bo[1 * nd + o] + (int64_t)c * n4 + k4i] * (double)(k4 + 1) : 0.0;
+              t = mfma(a, b, t);
+            }
+          }
+          // rows i5 = 4g + r, column i4 = c  ->  rho = i5 d4 + i4
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rho = (g + 4 * r) * d4 + c - rho0;
+            if (g + 4 * r < d5 && c < d4 && rho >= 0 && rho < nrow) Gs[rho * GS + p] = t[r];
+          }
+        } else {
+          const int p = h0 + u - nG, k3 = w3lo + 2 * p;
+          d4v t = d4v{0.0, 0.0, 0.0, 0.0};
+          if (p >= a3l && p <= b3l) {
+            for (int kk = 0; kk < nd; kk += 4) {
+              const int o = kk + g;
+              bool ok = false;
+              int k3i = 0, n3 = 0;
+              if (o < nd) {
+                const int lo3 = rng[6 * nd + o];
+                n3 = rng[7 * nd + o];
+                k3i = (k3 - lo3) >> 1;
+                ok = n3 > 0 && k3 >= lo3 && k3i < n3;
+              }
+              const double a = (ok && c < d3) ? B[bo[3 * nd + o] + (int64_t)c * n3 + k3i] * (double)(k3 + 1) : 0.0;
+              const double b = ok ? T2s[(o * 16 + c) * 16 + k3i] : 0.0;
+              t = mfma(a, b, t);
+            }
+          }
+          // rows i3 = 4g + r, column i2 = c  ->  sig = i3 d2 + i2
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (g + 4 * r < d3 && c < d2) Hs[p * HS + (g + 4 * r) * d2 + c] = t[r];
+        }
+      }
+      __syncthreads();
+
+      // ---- P = G U3 for the block's rows, written over G row tile by row tile (a wavefront
+      // reads and writes only its own row tiles, and finishes reading before it writes).
+      const int nq = ((b3l | 3) + 16) / 16;  // k3 column tiles (1 or 2)
+      for (int rt = w; rt < rtn; rt += WW) {
+        d4v pq0 = d4v{0.0, 0.0, 0.0, 0.0}, pq1 = d4v{0.0, 0.0, 0.0, 0.0};
+        for (int ks = g0; ks <= b4l; ks += 4) {
+          const int kp = ks + g;
+          const double a = Gs[(rt * 16 + c) * GS + kp];
+          const bool kin = kp >= a4l && kp <= b4l;
+          const int k4g = (w4lo + 2 * kp - rp.K_lo2[2]) >> 1;
+          const double *u3 = rp.U3 + ((u3base + xg) * nK4 + k4g) * nK3 + ((w3lo - rp.K_lo2[1]) >> 1);
+          const int q0 = c, q1 = 16 + c;
+          const double b0 = (kin && q0 >= a3l && q0 <= b3l) ? u3[q0] : 0.0;
+          pq0 = mfma(a, b0, pq0);
+          if (nq > 1) {
+            const double b1 = (kin && q1 >= a3l && q1 <= b3l) ? u3[q1] : 0.0;
+            pq1 = mfma(a, b1, pq1);
+          }
+        }
+        // Columns up to KW - 1 only: a row of G / P holds KW positions (the A update reads no
+        // further than the last active k3 position rounded up to 4, which is below KW).
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (c < KW) Gs[(rt * 16 + g + 4 * r) * GS + c] = pq0[r];
+          if (nq > 1 && 16 + c < KW) Gs[(rt * 16 + g + 4 * r) * GS + 16 + c] = pq1[r];
+        }
+      }
+      __syncthreads();
+
+      // ---- A(i1; rho, sig) += P H over the active k3 positions.
+      for (int ks = h0; ks <= b3l; ks += 4) {
+#pragma unroll
+        for (int j = 0; j < kMaxAcc; ++j) {
+          const int t = w + WW * j;
+          if (t < ntile) {
+            const int rt = t / CT, ct = t - rt * CT;
+            const double a = Gs[(rt * 16 + c) * GS + ks + g];
+            const double b = Hs[(ks + g) * HS + ct * 16 + c];
+            acc[j] = mfma(a, b, acc[j]);
+          }
+        }
+      }
+    }
+  }
+  // Flush the block's partial A(i1, ...): row rho = i5 d4 + i4, column sig = i3 d2 + i2.
+  const int64_t slice = (int64_t)d2 * d3 * d4 * d5;
+  double *out = rp.partial + ((int64_t)chunk_index * d1 + n1) * slice;
+#pragma unroll
+  for (int j = 0; j < kMaxAcc; ++j) {
+    const int t = w + WW * j;
+    if (t >= ntile) continue;
+    const int rt = t / CT, ct = t - rt * CT;
+    const int sig = ct * 16 + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rho = rho0 + rt * 16 + g + 4 * r;
+      if (rho < geo.R && sig < geo.C) {
+        const int i5 = rho / d4, i4 = rho - i5 * d4, i3 = sig / d2, i2 = sig - i3 * d2;
+        out[((i2 * d3 + i3) * d4 + i4) * d5 + i5] = acc[j][r];
+      }
+    }
+  }
+  __syncthreads();  // the next item reuses the LDS
+}
+
+__global__ __launch_bounds__(WT, 1) void wide_kernel(RingParams rp) {
+  extern __shared__ double smem[];
+  wide_item(rp, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+}
+
+// Persistent variant for batches: workgroups take (configuration, chunk, i1, row block) items of
+// a longest-first list from a counter; every item writes its own partial slice, so which
+// workgroup runs it does not matter.  The loop ends for every workgroup once the counter
+// passes nitems.
+__global__ __launch_bounds__(WT, 1) void wide_batch_kernel(const RingParams *cfgs, const int *items,
+                                                          int nitems, int *next) {
+  extern __shared__ double smem[];
+  __shared__ int it_s;
+  for (;;) {
+    if (threadIdx.x == 0) it_s = atomicAdd(next, 1);
+    __syncthreads();
+    const int it = it_s;
+    __syncthreads();
+    if (it >= nitems) break;
+    const int *p = items + 4 * it;
+    wide_item(cfgs[p[0]], p[1], p[2], p[3], smem);
+  }
+}
+
+}  // namespace
+
+size_t wide_smem_bytes(int nd, const int i_n[5], int kw, int nrb) { return wide_bytes(nd, i_n, kw, nrb); }
+
+int wide_row_blocks(const int i_n[5]) {
+  const int RT = (i_n[4] * i_n[3] + 15) / 16, CT = (i_n[2] * i_n[1] + 15) / 16;
+  for (int nrb = 1; nrb <= RT; ++nrb)
+    if (((RT + nrb - 1) / nrb) * CT <= WW * kMaxAcc) return nrb;
+  return 0;  // a single row tile already needs more accumulators than a workgroup holds
+}
+
+bool wide_fits(int nd, const int i_n[5], int kw, int nrb) {
+  return nrb > 0 && kw <= 32 && wide_bytes(nd, i_n, kw, nrb) <= kLdsBytes - 256;
+}
+
+hipError_t wide_init_attributes() {
+  hipError_t e = hipFuncSetAttribute((const void *)wide_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - 256));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void *)wide_batch_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - 256));
+}
+
+hipError_t launch_wide(const RingParams &rp, hipStream_t s) {
+  dim3 grid(rp.nchunk, rp.i_n[0], rp.nrb);
+  wide_kernel<<<grid, WT, wide_bytes(rp.nd, rp.i_n, rp.kw, rp.nrb), s>>>(rp);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems,
+                             size_t smem, int grid, int *next, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  wide_batch_kernel<<<grid, WT, smem, s>>>(cfgs_dev, items_dev, nitems, next);
+  return hipGetLastError();
+}
+
+}  // namespace eprl

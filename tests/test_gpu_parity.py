@@ -50,7 +50,7 @@ def torch():
     return torch
 
 
-@pytest.fixture(params=["shell", "ring"])
+@pytest.fixture(params=["shell", "ring", "ring_valu"])
 def algo(request, lib):
     """Run a test with one evaluation order of the shell sum, restoring the default after."""
     lib.set_algorithm(request.param)
@@ -62,7 +62,7 @@ def vertex_or_skip(lib, algo, *args, **kw):
     try:
         return lib.vertex_tensor(*args, **kw)
     except lib.EprlError as exc:
-        if algo == "ring" and exc.code == -4:
+        if algo in ("ring", "ring_valu") and exc.code == -4:
             pytest.skip("factorised path not applicable to these dimensions")
         raise
 
@@ -159,11 +159,12 @@ def test_vertex_tensor_small(lib, torch, algo, two_j, dl, seed):
     assert err <= TOL
 
 
-# Tile classes of the factorised order that the workloads above do not reach: 16-wide boundary
-# tiles with 8-wide virtual tiles (class 4: only i1 above 8), here with and without shells.
-TILE_CLASS_CASES = [([14, 15, 15, 12, 3, 16, 1, 0, 16, 3], 3, 51, 4),
-                    ([14, 8, 13, 11, 12, 8, 2, 5, 7, 6], 0, 52, 4),
-                    ([13, 10, 12, 11, 0, 5, 10, 13, 9, 0], 0, 53, 4)]
+# Boundary dimensions above 8 with every virtual range at most 8 (only i1 above 8), with and
+# without shells: "ring" runs them in the all-matrix-core kernel (class 8), "ring_valu" in the
+# 16-wide vector-ALU kernel with 8-wide virtual tiles (class 4), which no workload above reaches.
+TILE_CLASS_CASES = [([14, 15, 15, 12, 3, 16, 1, 0, 16, 3], 3, 51, 8),
+                    ([14, 8, 13, 11, 12, 8, 2, 5, 7, 6], 0, 52, 8),
+                    ([13, 10, 12, 11, 0, 5, 10, 13, 9, 0], 0, 53, 8)]
 
 
 @pytest.mark.parametrize("two_j,dl,seed,cls", TILE_CLASS_CASES)
@@ -419,7 +420,7 @@ def test_autotune(lib, torch, two_j, dl, seed):
         (batched,) = lib.vertex_tensor_batched([(two_j, dl)], 1.2, [bd])
         assert torch.equal(batched, a)
         with pytest.raises(lib.EprlError):
-            lib.set_tuning(8, 0, -1)
+            lib.set_tuning(9, 0, -1)
         with pytest.raises(lib.EprlError):
             lib.set_tuning(cls, 0, 3)
     finally:
