@@ -1,0 +1,434 @@
+// Adjoint of the boundary contraction in the factorised (ring) order.
+//
+// With the boundary vectors inserted (p_a(i) = sqrt(2i+1) psi_a(i), and for the four boosted
+// edges u_e(k; l_e) = sum_i p_e(i) M_e(l_e)[i, k], M_e = (2k+1) B_e), eq. (vertex-ampl) contracted
+// with psi is, for each x of eq. (15j) and each shell, the trace of a closed chain of the signed
+// 6j tables (the ones of the factorised vertex kernels, whose x-sum gives W exactly):
+//   F = sum_{shells, x} sum_{i1} p1(i1) [U1 D5 U2 D4 U3 D3 U4 D2 U5](i1, i1),   D_e = diag(u_e).
+// The derivative with respect to a booster entry is
+//   dF/dB_e(l_e)[i, k] = (2k+1) p_e(i) G_e(k; l_e),
+//   G_e(k; l_e) = sum over the shells containing l_e and over x of the chain with u_e(k) taken out.
+// With the core (l24, l25, l34, l35) and x fixed, l45 enters only the left half of the chain and
+// l23 only the right half, so (all matrices at most 16 x 32):
+//   V2_o(k3, i1)  = sum_k2 U4(k3, k2; l23=o) u2(k2; o) U5(k2, i1)          X2 = sum_o D3_o V2_o
+//   R4(k4, i1)    = sum_k3 U3(k4, k3) X2(k3, i1)
+//   Z5_o(i1, k4)  = sum_k5 p1(i1) U1(i1, k5) u5(k5; l45=o) U2(k5, k4; o)   X5 = sum_o Z5_o D4_o
+//   G4_o(k4)     += sum_i1 Z5_o(i1, k4) R4(k4, i1)
+//   G5_o(k5)     += sum_i1 p1(i1) U1(i1, k5) sum_k4 U2(k5, k4; o) u4(k4; o) R4(k4, i1)
+//   R3(i1, k3)    = sum_k4 X5(i1, k4) U3(k4, k3)
+//   G3_o(k3)     += sum_i1 R3(i1, k3) V2_o(k3, i1)
+//   G2_o(k2)     += sum_i1 U5(k2, i1) sum_k3 R3(i1, k3) u3(k3; o) U4(k3, k2; o)
+// per core and x: O(nd d^3) complex multiply-adds instead of the O(nd^2 d^3) of the per-shell
+// traces.  One workgroup per core accumulates its G vectors over x and writes them out; a second
+// kernel sums, for every booster entry, the G of the cores that share its block, in a fixed
+// order (no atomics: the result is bitwise repeatable).
+#include "eprl_internal.hpp"
+
+namespace eprl {
+
+namespace {
+
+struct cplx {
+  double re, im;
+};
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
+__device__ __forceinline__ cplx cfma(cplx acc, cplx a, double s) {
+  return {acc.re + a.re * s, acc.im + a.im * s};
+}
+__device__ __forceinline__ cplx load_c(const double *p, int i) { return {p[2 * i], p[2 * i + 1]}; }
+__device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
+constexpr int AT = 256;  // threads per workgroup
+
+// The five boundary vectors (device, complex interleaved), passed by value.
+struct PsiPtrs {
+  const double *p[5];
+};
+constexpr int KL = 16;   // k values of one block (virtual intertwiner ranges are at most 16)
+constexpr int IW = 16;   // i1 values
+constexpr int KWIN = 32; // k values of a core window (union over l45 or l23)
+
+// LDS layout (complex unless noted); per-spin arrays are [nd][KL].
+struct AdjGeom {
+  int p1, u5, u4, u2, u3, g5, g4, g3, g2;     // [IW] and [nd][KL] vectors
+  int v2;                                      // [nd][KL k3][IW]
+  int x2, r4, x5, r3;                          // [KWIN][IW] or [IW][KWIN]
+  int z5, q5, s2;                              // [IW][KL], [KL][IW], [IW][KL] scratch
+  int u1s, u5s, u3s;                           // real: [IW][KWIN], [KWIN][IW], [KWIN][KWIN]
+  int meta;                                    // ints: rng [8][nd], then int64 bo [4][nd]
+  size_t bytes;
+};
+
+__host__ __device__ inline AdjGeom adj_geom(int nd) {
+  AdjGeom g;
+  int c = 0;  // in complex units (16 bytes)
+  g.p1 = c; c += IW;
+  g.u5 = c; c += nd * KL;
+  g.u4 = c; c += nd * KL;
+  g.u2 = c; c += nd * KL;
+  g.u3 = c; c += nd * KL;
+  g.g5 = c; c += nd * KL;
+  g.g4 = c; c += nd * KL;
+  g.g3 = c; c += nd * KL;
+  g.g2 = c; c += nd * KL;
+  g.v2 = c; c += nd * KL * IW;
+  g.x2 = c; c += KWIN * IW;
+  g.r4 = c; c += KWIN * IW;
+  g.x5 = c; c += IW * KWIN;
+  g.r3 = c; c += IW * KWIN;
+  g.z5 = c; c += IW * KL;
+  g.q5 = c; c += KL * IW;
+  g.s2 = c; c += IW * KL;
+  int d = 2 * c;  // in doubles
+  g.u1s = d; d += IW * KWIN;
+  g.u5s = d; d += KWIN * IW;
+  g.u3s = d; d += KWIN * KWIN;
+  g.meta = d;
+  g.bytes = sizeof(double) * (size_t)d + sizeof(int) * 8 * (size_t)nd + sizeof(int64_t) * 4 * (size_t)nd;
+  return g;
+}
+
+__global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs psi, double *gbuf) {
+  extern __shared__ double sm[];
+  const int nd = rp.nd, nd3 = nd * nd * nd;
+  const AdjGeom geo = adj_geom(nd);
+  cplx *cs = reinterpret_cast<cplx *>(sm);
+  cplx *P1 = cs + geo.p1, *u5 = cs + geo.u5, *u4 = cs + geo.u4, *u2 = cs + geo.u2, *u3 = cs + geo.u3;
+  cplx *G5 = cs + geo.g5, *G4 = cs + geo.g4, *G3 = cs + geo.g3, *G2 = cs + geo.g2;
+  cplx *V2 = cs + geo.v2, *X2 = cs + geo.x2, *R4 = cs + geo.r4, *X5 = cs + geo.x5, *R3 = cs + geo.r3;
+  cplx *Z5 = cs + geo.z5, *Q5 = cs + geo.q5, *S2 = cs + geo.s2;
+  double *U1s = sm + geo.u1s, *U5s = sm + geo.u5s, *U3s = sm + geo.u3s;
+  int *rng = reinterpret_cast<int *>(sm + geo.meta);
+  int64_t *bo = reinterpret_cast<int64_t *>(rng + 8 * nd);
+
+  const int tid = threadIdx.x;
+  const int core = blockIdx.x;
+  const int o24 = core / nd3, o25 = (core / (nd * nd)) % nd, o34 = (core / nd) % nd, o35 = core % nd;
+  const int *J = rp.two_j;
+  const int l24 = J[L24] + 2 * o24, l25 = J[L25] + 2 * o25, l35 = J[L35] + 2 * o35;
+  const int d1 = rp.i_n[0];
+  const int NX = rp.NX, nK2 = rp.K_n[0], nK3 = rp.K_n[1], nK4 = rp.K_n[2], nK5 = rp.K_n[3];
+  const double *B = rp.B;
+
+  for (int o = tid; o < nd; o += AT) {
+    const int t5 = (o25 * nd + o35) * nd + o, t4 = (o * nd + o24) * nd + o34;
+    const int t2 = (o * nd + o24) * nd + o25, t3 = (o34 * nd + o35) * nd + o;
+    int n5 = rp.kr[(3 * nd3 + t5) * 2 + 1], n4 = rp.kr[(2 * nd3 + t4) * 2 + 1];
+    int n2 = rp.kr[(0 * nd3 + t2) * 2 + 1], n3 = rp.kr[(1 * nd3 + t3) * 2 + 1];
+    // A spin whose pair of ranges has an empty member closes no shell.
+    if (n5 == 0 || n4 == 0) n5 = n4 = 0;
+    if (n2 == 0 || n3 == 0) n2 = n3 = 0;
+    rng[0 * nd + o] = rp.kr[(3 * nd3 + t5) * 2];
+    rng[1 * nd + o] = n5;
+    rng[2 * nd + o] = rp.kr[(2 * nd3 + t4) * 2];
+    rng[3 * nd + o] = n4;
+    rng[4 * nd + o] = rp.kr[(0 * nd3 + t2) * 2];
+    rng[5 * nd + o] = n2;
+    rng[6 * nd + o] = rp.kr[(1 * nd3 + t3) * 2];
+    rng[7 * nd + o] = n3;
+    bo[0 * nd + o] = rp.boff[3 * nd3 + t5];
+    bo[1 * nd + o] = rp.boff[2 * nd3 + t4];
+    bo[2 * nd + o] = rp.boff[0 * nd3 + t2];
+    bo[3 * nd + o] = rp.boff[1 * nd3 + t3];
+  }
+  for (int q = tid; q < 4 * nd * KL; q += AT) G5[q] = cplx{0.0, 0.0};  // G5, G4, G3, G2 are adjacent
+  for (int q = tid; q < IW; q += AT)
+    P1[q] = q < d1 ? cscale(load_c(psi.p[0], q), __builtin_sqrt((double)(rp.i_lo2[0] + 2 * q + 1)))
+                   : cplx{0.0, 0.0};
+  __syncthreads();
+  // Contracted boosters u_e(k; l) of this core: edge slot s = 0 u5 (l45), 1 u4 (l45), 2 u2 (l23),
+  // 3 u3 (l23); psi of edges 5, 4, 2, 3.
+  for (int q = tid; q < 4 * nd * KL; q += AT) {
+    const int s = q / (nd * KL), o = (q / KL) % nd, k = q % KL;
+    const int ri = s == 0 ? 0 : s == 1 ? 2 : s == 2 ? 4 : 6;
+    const int lo = rng[ri * nd + o], n = rng[(ri + 1) * nd + o];
+    const int e = s == 0 ? 4 : s == 1 ? 3 : s == 2 ? 1 : 2;  // boundary index of the edge
+    cplx u{0.0, 0.0};
+    if (k < n) {
+      const double w = (double)(lo + 2 * k + 1);
+      const int64_t off = bo[s * nd + o];
+      for (int i = 0; i < rp.i_n[e]; ++i) {
+        const cplx p = cscale(load_c(psi.p[e], i), __builtin_sqrt((double)(rp.i_lo2[e] + 2 * i + 1)));
+        u = cfma(u, p, B[off + (int64_t)i * n + k] * w);
+      }
+    }
+    cs[(s == 0 ? geo.u5 : s == 1 ? geo.u4 : s == 2 ? geo.u2 : geo.u3) + o * KL + k] = u;
+  }
+  // Core windows of k4 (over l45), k3 (over l23), k5 (over l45) and k2 (over l23).
+  int w4lo = 1 << 30, w4hi = -1, w3lo = 1 << 30, w3hi = -1, w5lo = 1 << 30, w2lo = 1 << 30;
+  int w5hi = -1, w2hi = -1;
+  for (int o = 0; o < nd; ++o) {
+    if (rng[3 * nd + o] > 0) {
+      w4lo = imin(w4lo, rng[2 * nd + o]);
+      w4hi = imax(w4hi, rng[2 * nd + o] + 2 * (rng[3 * nd + o] - 1));
+      w5lo = imin(w5lo, rng[0 * nd + o]);
+      w5hi = imax(w5hi, rng[0 * nd + o] + 2 * (rng[1 * nd + o] - 1));
+    }
+    if (rng[7 * nd + o] > 0) {
+      w3lo = imin(w3lo, rng[6 * nd + o]);
+      w3hi = imax(w3hi, rng[6 * nd + o] + 2 * (rng[7 * nd + o] - 1));
+      w2lo = imin(w2lo, rng[4 * nd + o]);
+      w2hi = imax(w2hi, rng[4 * nd + o] + 2 * (rng[5 * nd + o] - 1));
+    }
+  }
+  const bool live = w4hi >= 0 && w3hi >= 0;
+  const int nw4 = live ? (w4hi - w4lo) / 2 + 1 : 0, nw3 = live ? (w3hi - w3lo) / 2 + 1 : 0;
+  const int nw5 = live ? (w5hi - w5lo) / 2 + 1 : 0, nw2 = live ? (w2hi - w2lo) / 2 + 1 : 0;
+  const int64_t u3base = (((int64_t)o24 * nd + o34) * nd + o35) * NX;
+  const int xhi_g = rp.X_lo2 + 2 * (NX - 1);
+  // x closes (i1 l25 x) for some i1, (k4 l35 x) and (k3 l24 x) for some k4, k3 of the windows.
+  int xlo = 0, xhi = -1;
+  if (live) {
+    const int i1lo = rp.i_lo2[0], i1hi = rp.i_lo2[0] + 2 * (d1 - 1);
+    xlo = imax(rp.X_lo2, l25 > i1hi ? l25 - i1hi : (i1lo > l25 ? i1lo - l25 : ((l25 - i1lo) & 1)));
+    xhi = imin(xhi_g, i1hi + l25);
+  }
+  for (int x = xlo; x <= xhi; x += 2) {
+    const int a4 = imax(w4lo, iabs(l35 - x)), b4 = imin(w4hi, l35 + x);
+    const int a3 = imax(w3lo, iabs(l24 - x)), b3 = imin(w3hi, l24 + x);
+    if (a4 > b4 || a3 > b3) continue;  // uniform
+    const int xg = (x - rp.X_lo2) / 2;
+    __syncthreads();  // previous x's readers are done
+    // Table slices of this x: U1(i1, k5), U5(k2, i1), U3(k4, k3) over the core windows.
+    for (int q = tid; q < IW * KWIN; q += AT) {
+      const int i = q / KWIN, p = q % KWIN;
+      double v1 = 0.0, v5 = 0.0;
+      if (i < d1 && p < nw5)
+        v1 = rp.U1[(((int64_t)o25 * NX + xg) * d1 + i) * nK5 + ((w5lo - rp.K_lo2[3]) >> 1) + p];
+      if (i < d1 && p < nw2)
+        v5 = rp.U5[(((int64_t)o25 * NX + xg) * nK2 + ((w2lo - rp.K_lo2[0]) >> 1) + p) * d1 + i];
+      U1s[i * KWIN + p] = v1;
+      U5s[p * IW + i] = v5;
+    }
+    for (int q = tid; q < KWIN * KWIN; q += AT) {
+      const int p4 = q / KWIN, p3 = q % KWIN;
+      double v = 0.0;
+      if (p4 < nw4 && p3 < nw3)
+        v = rp.U3[((u3base + xg) * nK4 + ((w4lo - rp.K_lo2[2]) >> 1) + p4) * nK3 +
+                  ((w3lo - rp.K_lo2[1]) >> 1) + p3];
+      U3s[q] = v;
+    }
+    __syncthreads();
+    // V2_o(k3, i1) = sum_k2 U4(k3, k2; o) u2(k2; o) U5(k2, i1) for every l23 = o.
+    for (int q = tid; q < nd * KL * IW; q += AT) {
+      const int o = q / (KL * IW), k3i = (q / IW) % KL, i = q % IW;
+      const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
+      cplx v{0.0, 0.0};
+      if (k3i < n3 && i < d1) {
+        const int k3g = (lo3 + 2 * k3i - rp.K_lo2[1]) >> 1;
+        const double *u4r = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g) * nK2 +
+                            ((lo2 - rp.K_lo2[0]) >> 1);
+        const int p2 = (lo2 - w2lo) >> 1;
+        for (int k2i = 0; k2i < n2; ++k2i)
+          v = cfma(v, u2[o * KL + k2i], u4r[k2i] * U5s[(p2 + k2i) * IW + i]);
+      }
+      V2[q] = v;
+    }
+    __syncthreads();
+    // X2(k3, i1) = sum_o u3(k3; o) V2_o(k3, i1), k3 over the core window.
+    for (int q = tid; q < KWIN * IW; q += AT) {
+      const int p3 = q / IW, i = q % IW;
+      cplx v{0.0, 0.0};
+      if (p3 < nw3) {
+        const int k3 = w3lo + 2 * p3;
+        for (int o = 0; o < nd; ++o) {
+          const int lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o], k3i = (k3 - lo3) >> 1;
+          if (n3 > 0 && k3 >= lo3 && k3i < n3) v = cadd(v, cmul(u3[o * KL + k3i], V2[(o * KL + k3i) * IW + i]));
+        }
+      }
+      X2[q] = v;
+    }
+    __syncthreads();
+    // R4(k4, i1) = sum_k3 U3(k4, k3) X2(k3, i1); X5 cleared.
+    for (int q = tid; q < KWIN * IW; q += AT) {
+      const int p4 = q / IW, i = q % IW;
+      cplx v{0.0, 0.0};
+      if (p4 < nw4)
+        for (int p3 = 0; p3 < nw3; ++p3) v = cfma(v, X2[p3 * IW + i], U3s[p4 * KWIN + p3]);
+      R4[q] = v;
+      X5[q] = cplx{0.0, 0.0};
+    }
+    __syncthreads();
+    // Left half, one l45 = o at a time.
+    for (int o = 0; o < nd; ++o) {
+      const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
+      if (n4 == 0) continue;  // uniform
+      const int p5 = (lo5 - w5lo) >> 1, p4 = (lo4 - w4lo) >> 1;
+      const double *u2b = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5 + ((lo5 - rp.K_lo2[3]) >> 1)) * nK4 +
+                          ((lo4 - rp.K_lo2[2]) >> 1);
+      // Z5(i1, k4) = p1(i1) sum_k5 U1(i1, k5) u5(k5) U2(k5, k4)
+      for (int q = tid; q < IW * KL; q += AT) {
+        const int i = q / KL, k4i = q % KL;
+        cplx v{0.0, 0.0};
+        if (i < d1 && k4i < n4) {
+          for (int k5i = 0; k5i < n5; ++k5i)
+            v = cfma(v, u5[o * KL + k5i], U1s[i * KWIN + p5 + k5i] * u2b[(int64_t)k5i * nK4 + k4i]);
+          v = cmul(v, P1[i]);
+        }
+        Z5[q] = v;
+      }
+      // Q5(k5, i1) = sum_k4 U2(k5, k4) u4(k4) R4(k4, i1)
+      for (int q = tid; q < KL * IW; q += AT) {
+        const int k5i = q / IW, i = q % IW;
+        cplx v{0.0, 0.0};
+        if (k5i < n5 && i < d1)
+          for (int k4i = 0; k4i < n4; ++k4i)
+            v = cadd(v, cmul(u4[o * KL + k4i], cscale(R4[(p4 + k4i) * IW + i], u2b[(int64_t)k5i * nK4 + k4i])));
+        Q5[q] = v;
+      }
+      __syncthreads();
+      // G4(k4) += sum_i1 Z5(i1, k4) R4(k4, i1);  G5(k5) += sum_i1 p1(i1) U1(i1, k5) Q5(k5, i1);
+      // X5(i1, k4) += Z5(i1, k4) u4(k4)
+      for (int q = tid; q < 2 * KL + IW * KL; q += AT) {
+        if (q < KL) {
+          const int k4i = q;
+          if (k4i < n4) {
+            cplx v{0.0, 0.0};
+            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(Z5[i * KL + k4i], R4[(p4 + k4i) * IW + i]));
+            G4[o * KL + k4i] = cadd(G4[o * KL + k4i], v);
+          }
+        } else if (q < 2 * KL) {
+          const int k5i = q - KL;
+          if (k5i < n5) {
+            cplx v{0.0, 0.0};
+            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(P1[i], cscale(Q5[k5i * IW + i], U1s[i * KWIN + p5 + k5i])));
+            G5[o * KL + k5i] = cadd(G5[o * KL + k5i], v);
+          }
+        } else {
+          const int r = q - 2 * KL, i = r / KL, k4i = r % KL;
+          if (i < d1 && k4i < n4) X5[i * KWIN + p4 + k4i] = cadd(X5[i * KWIN + p4 + k4i], cmul(Z5[r], u4[o * KL + k4i]));
+        }
+      }
+      __syncthreads();
+    }
+    // R3(i1, k3) = sum_k4 X5(i1, k4) U3(k4, k3)
+    for (int q = tid; q < IW * KWIN; q += AT) {
+      const int i = q / KWIN, p3 = q % KWIN;
+      cplx v{0.0, 0.0};
+      if (p3 < nw3)
+        for (int p4 = 0; p4 < nw4; ++p4) v = cfma(v, X5[i * KWIN + p4], U3s[p4 * KWIN + p3]);
+      R3[q] = v;
+    }
+    __syncthreads();
+    // Right half, one l23 = o at a time.
+    for (int o = 0; o < nd; ++o) {
+      const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
+      if (n3 == 0) continue;  // uniform
+      const int p3 = (lo3 - w3lo) >> 1, p2 = (lo2 - w2lo) >> 1;
+      const double *u4b = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + ((lo3 - rp.K_lo2[1]) >> 1)) * nK2 +
+                          ((lo2 - rp.K_lo2[0]) >> 1);
+      // G3(k3) += sum_i1 R3(i1, k3) V2(k3, i1);  S2(i1, k2) = sum_k3 R3(i1, k3) u3(k3) U4(k3, k2)
+      for (int q = tid; q < KL + IW * KL; q += AT) {
+        if (q < KL) {
+          const int k3i = q;
+          if (k3i < n3) {
+            cplx v{0.0, 0.0};
+            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(R3[i * KWIN + p3 + k3i], V2[(o * KL + k3i) * IW + i]));
+            G3[o * KL + k3i] = cadd(G3[o * KL + k3i], v);
+          }
+        } else {
+          const int r = q - KL, i = r / KL, k2i = r % KL;
+          cplx v{0.0, 0.0};
+          if (i < d1 && k2i < n2)
+            for (int k3i = 0; k3i < n3; ++k3i)
+              v = cadd(v, cmul(u3[o * KL + k3i], cscale(R3[i * KWIN + p3 + k3i], u4b[(int64_t)k3i * nK2 + k2i])));
+          S2[r] = v;
+        }
+      }
+      __syncthreads();
+      // G2(k2) += sum_i1 S2(i1, k2) U5(k2, i1)
+      for (int k2i = tid; k2i < n2; k2i += AT) {
+        cplx v{0.0, 0.0};
+        for (int i = 0; i < d1; ++i) v = cfma(v, S2[i * KL + k2i], U5s[(p2 + k2i) * IW + i]);
+        G2[o * KL + k2i] = cadd(G2[o * KL + k2i], v);
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  // gbuf[core][slot][o][k], slots in booster-edge order: 0 G2, 1 G3, 2 G4, 3 G5.
+  double *out = gbuf + (int64_t)core * 4 * nd * KL * 2;
+  for (int q = tid; q < 4 * nd * KL; q += AT) {
+    const int s = q / (nd * KL), r = q % (nd * KL);
+    const cplx v = (s == 0 ? G2 : s == 1 ? G3 : s == 2 ? G4 : G5)[r];
+    out[2 * q] = v.re;
+    out[2 * q + 1] = v.im;
+  }
+}
+
+// One thread per booster entry (edge e, triple t, row i, column k): the sum over the nd^2 cores
+// that contain the block, in a fixed order, times g (2k+1) p_e(i).
+__global__ void adjoint_ring_reduce_kernel(RingParams rp, PsiPtrs psi, const double *gbuf, double gre,
+                                           double gim, double *grad_b) {
+  const int nd = rp.nd, nd3 = nd * nd * nd;
+  const int64_t total = rp.boff[4 * nd3];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  int lo = 0, hi = 4 * nd3 - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (rp.boff[mid] <= idx) lo = mid; else hi = mid - 1;
+  }
+  const int e = lo / nd3, t = lo % nd3;
+  const int kn = rp.kr[(e * nd3 + t) * 2 + 1], klo = rp.kr[(e * nd3 + t) * 2];
+  const int64_t within = idx - rp.boff[lo];
+  const int i = (int)(within / kn), k = (int)(within % kn);
+  const int a = t / (nd * nd), b = (t / nd) % nd, c = t % nd;
+  // The block's triple in shell coordinates and the core coordinates (o24, o25, o34, o35) that
+  // run free: e2 (l23, l24, l25): o = a, (o24, o25) = (b, c), free (o34, o35);
+  // e3 (l34, l35, l23): o = c, (o34, o35) = (a, b), free (o24, o25);
+  // e4 (l45, l24, l34): o = a, (o24, o34) = (b, c), free (o25, o35);
+  // e5 (l25, l35, l45): o = c, (o25, o35) = (a, b), free (o24, o34).
+  const int o = (e == 0 || e == 2) ? a : c;
+  double sre = 0.0, sim = 0.0;
+  for (int f = 0; f < nd * nd; ++f) {
+    const int p = f / nd, q = f % nd;
+    int o24, o25, o34, o35;
+    if (e == 0) { o24 = b; o25 = c; o34 = p; o35 = q; }
+    else if (e == 1) { o34 = a; o35 = b; o24 = p; o25 = q; }
+    else if (e == 2) { o24 = b; o34 = c; o25 = p; o35 = q; }
+    else { o25 = a; o35 = b; o24 = p; o34 = q; }
+    const int core = ((o24 * nd + o25) * nd + o34) * nd + o35;
+    const double *g = gbuf + (((int64_t)core * 4 + e) * nd + o) * KL * 2 + 2 * k;
+    sre += g[0];
+    sim += g[1];
+  }
+  const cplx pe = cscale(load_c(psi.p[e + 1], i), __builtin_sqrt((double)(rp.i_lo2[e + 1] + 2 * i + 1)));
+  const cplx v = cmul(cscale(cmul(pe, cplx{sre, sim}), (double)(klo + 2 * k + 1)), cplx{gre, gim});
+  grad_b[2 * idx] = v.re;
+  grad_b[2 * idx + 1] = v.im;
+}
+
+}  // namespace
+
+size_t adjoint_ring_smem(int nd) { return adj_geom(nd).bytes; }
+size_t adjoint_ring_gbuf_bytes(int nd) {
+  return sizeof(double) * 2 * (size_t)nd * nd * nd * nd * 4 * nd * KL;
+}
+
+hipError_t adjoint_ring_init_attributes() {
+  return hipFuncSetAttribute((const void *)adjoint_ring_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)adj_geom(kAdjRingMaxNd).bytes);
+}
+
+hipError_t launch_adjoint_ring(const RingParams &rp, const double *const psi[5], double *gbuf,
+                               int64_t total, double gre, double gim, double *grad_b, hipStream_t s) {
+  PsiPtrs pp;
+  for (int a = 0; a < 5; ++a) pp.p[a] = psi[a];
+  const int nd = rp.nd;
+  if (nd > kAdjRingMaxNd) return hipErrorInvalidValue;
+  adjoint_ring_kernel<<<nd * nd * nd * nd, AT, adj_geom(nd).bytes, s>>>(rp, pp, gbuf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (total <= 0) return hipSuccess;
+  adjoint_ring_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(rp, pp, gbuf, gre, gim, grad_b);
+  return hipGetLastError();
+}
+
+}  // namespace eprl

@@ -377,25 +377,8 @@ ReduceParams reduce_params(const Plan &p, const double *partial, int nchunk, dou
   return rp;
 }
 
-// Factorised evaluation over all shells (one launch of the ring kernel, then the reduction).
-int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int accumulate,
-              double *A, const Plan &probe) {
-  const int cls = probe.ring_cls;
-  const int target = c->tune_wg[cls] > 0 ? c->tune_wg[cls] : kRingTargetWG;
-  std::vector<int> key(two_j, two_j + 10);
-  key.push_back(dl);
-  key.push_back(target);
-  key.push_back(cls);
-  if (key != c->sched_key) {
-    c->sched_nchunk = ring_schedule(probe, target, c->sched_bounds);
-    c->sched_key = key;
-  }
-  const std::vector<int> &bounds = c->sched_bounds;
-  const int nchunk = c->sched_nchunk;
-  const size_t pbytes = align_up((size_t)nchunk * probe.a_size * sizeof(double), 256);
-  Prepared prep;
-  int rc = prepare(c, two_j, dl, pbytes, prep, true, &bounds, &probe);
-  if (rc) return rc;
+// Kernel parameters of the factorised order for a prepared configuration (ring tables).
+RingParams ring_params(const Prepared &prep, const double *B) {
   const Plan &p = prep.plan;
   RingParams rp;
   std::memset(&rp, 0, sizeof(rp));
@@ -419,6 +402,32 @@ int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int acc
   rp.B = B;
   rp.boff = prep.boff;
   rp.kr = prep.kr;
+  rp.kw = p.ring_kw;
+  rp.nrb = ring_row_blocks(p);
+  return rp;
+}
+
+// Factorised evaluation over all shells (one launch of the ring kernel, then the reduction).
+int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int accumulate,
+              double *A, const Plan &probe) {
+  const int cls = probe.ring_cls;
+  const int target = c->tune_wg[cls] > 0 ? c->tune_wg[cls] : kRingTargetWG;
+  std::vector<int> key(two_j, two_j + 10);
+  key.push_back(dl);
+  key.push_back(target);
+  key.push_back(cls);
+  if (key != c->sched_key) {
+    c->sched_nchunk = ring_schedule(probe, target, c->sched_bounds);
+    c->sched_key = key;
+  }
+  const std::vector<int> &bounds = c->sched_bounds;
+  const int nchunk = c->sched_nchunk;
+  const size_t pbytes = align_up((size_t)nchunk * probe.a_size * sizeof(double), 256);
+  Prepared prep;
+  int rc = prepare(c, two_j, dl, pbytes, prep, true, &bounds, &probe);
+  if (rc) return rc;
+  const Plan &p = prep.plan;
+  RingParams rp = ring_params(prep, B);
   rp.partial = reinterpret_cast<double *>(prep.tail);
   rp.bounds = prep.sched;
   rp.nchunk = nchunk;
@@ -1157,6 +1166,18 @@ int eprl_contract_boundary_adjoint(eprl_ctx *c, const int two_j[10], int dl, con
   if (!grad_boosters) return EPRL_OK;
   if (!B) return fail(c, EPRL_EINVAL, "null booster pointer");
   if (probe.kmax > 16) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
+  if (c->algo != EPRL_ALGO_SHELL && probe.ring_KW != 0 && probe.nd <= kAdjRingMaxNd) {
+    // Factorised order: per-core G vectors, then a fixed-order sum per booster entry.
+    Prepared prep;
+    rc = prepare(c, two_j, dl, align_up(adjoint_ring_gbuf_bytes(probe.nd), 256), prep, true, nullptr,
+                 &probe);
+    if (rc) return rc;
+    RingParams rp = ring_params(prep, B);
+    TimedLaunch tl(c, 3);
+    HIP_TRY(c, launch_adjoint_ring(rp, psi, reinterpret_cast<double *>(prep.tail), prep.plan.boff.back(),
+                                   grad_F[0], grad_F[1], grad_boosters, c->stream));
+    return EPRL_OK;
+  }
   const int kpad = std::max(probe.kmax, 1);
   const size_t gbytes = align_up((size_t)probe.nshell * 4 * kpad * 2 * sizeof(double), 256);
   Prepared prep;

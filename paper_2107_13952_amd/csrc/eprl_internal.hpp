@@ -194,6 +194,15 @@ struct AdjointParams {
   int kpad;
 };
 hipError_t launch_adjoint_shells(const AdjointParams &ap, hipStream_t s);
+// Adjoint in the factorised order (one workgroup per core, then a fixed-order sum per booster
+// entry of `total`); the per-core G vectors go to gbuf (adjoint_ring_gbuf_bytes).  Applies where
+// the factorised vertex kernels do, with dl + 1 <= kAdjRingMaxNd.
+constexpr int kAdjRingMaxNd = 11;
+size_t adjoint_ring_smem(int nd);
+size_t adjoint_ring_gbuf_bytes(int nd);
+hipError_t adjoint_ring_init_attributes();
+hipError_t launch_adjoint_ring(const RingParams &rp, const double *const psi[5], double *gbuf,
+                               int64_t total, double gre, double gim, double *grad_b, hipStream_t s);
 hipError_t launch_adjoint_reduce(const AdjointParams &ap, int64_t total, double gre, double gim,
                                  double *grad_b, hipStream_t s);
 

@@ -724,7 +724,9 @@ hipError_t ring_init_attributes() {
     hipError_t e = dispatch(cls, 0, [](auto v) { return decltype(v)::init(); });
     if (e != hipSuccess) return e;
   }
-  return wide_init_attributes();
+  hipError_t e = wide_init_attributes();
+  if (e != hipSuccess) return e;
+  return adjoint_ring_init_attributes();
 }
 
 hipError_t launch_ring(const RingParams &rp, int cls, int stg, hipStream_t s) {
