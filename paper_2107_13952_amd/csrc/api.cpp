@@ -581,18 +581,22 @@ hipError_t enqueue_batch(eprl_ctx *c) {
     const int nit = seq.cls_begin[cls + 1] - seq.cls_begin[cls];
     if (nit == 0) continue;
     if (cls == kWideClass) {
-      // One 8-wavefront workgroup per CU, LDS sized for the largest configuration of the class.
-      size_t shm = 0;
+      // One 8-wavefront workgroup per CU, LDS sized for the largest configuration of the class;
+      // booster blocks staged when every configuration's fit.
+      size_t shm = 0, shm_stg = 0;
+      bool stg = true;
       for (const BatchEntry &b : seq.ent)
         if (b.ring && b.plan.ring_cls == kWideClass) {
           int dims[5];
           for (int q = 0; q < 5; ++q) dims[q] = b.plan.i[q].n;
-          shm = std::max(shm, wide_smem_bytes(b.plan.nd, dims, b.plan.ring_kw, b.plan.ring_nrb));
+          shm = std::max(shm, wide_smem_bytes(b.plan.nd, dims, b.plan.ring_kw, b.plan.ring_nrb, false));
+          shm_stg = std::max(shm_stg, wide_smem_bytes(b.plan.nd, dims, b.plan.ring_kw, b.plan.ring_nrb, true));
+          stg = stg && wide_fits(b.plan.nd, dims, b.plan.ring_kw, b.plan.ring_nrb, true);
         }
       TimedLaunch tl(c, 6);
       e = launch_wide_batch(reinterpret_cast<const RingParams *>(ws + seq.params_off),
                             reinterpret_cast<const int *>(ws + seq.items_off) + 4 * seq.cls_begin[cls],
-                            nit, shm, std::min(nit, seq.ncu), counters + cls, c->stream);
+                            nit, stg ? shm_stg : shm, stg, std::min(nit, seq.ncu), counters + cls, c->stream);
       continue;
     }
     // Enough workgroups to fill the chip at the occupancy the tile class allows.

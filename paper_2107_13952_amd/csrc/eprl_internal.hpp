@@ -136,15 +136,16 @@ constexpr int kWideClass = 8;
 constexpr int kRingClasses = 9;
 // Largest dl + 1 the wide kernel takes (its per-spin tiles must fit in LDS beside G and H).
 constexpr int kWideMaxNd = 11;
-size_t wide_smem_bytes(int nd, const int i_n[5], int kw, int nrb);
+// LDS bytes of the wide kernel; stg: with the core's booster blocks staged.
+size_t wide_smem_bytes(int nd, const int i_n[5], int kw, int nrb, bool stg);
 // Row blocks of A(i1) per work item so that each wavefront holds at most 12 accumulator tiles
 // (0 when even one row tile needs more).
 int wide_row_blocks(const int i_n[5]);
-bool wide_fits(int nd, const int i_n[5], int kw, int nrb);
+bool wide_fits(int nd, const int i_n[5], int kw, int nrb, bool stg = false);
 hipError_t wide_init_attributes();
 hipError_t launch_wide(const RingParams &rp, hipStream_t s);
 hipError_t launch_wide_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems,
-                             size_t smem, int grid, int *next, hipStream_t s);
+                             size_t smem, bool stg, int grid, int *next, hipStream_t s);
 // Splits the cores of the factorised path, for each i1, into chunks of equal estimated cost
 // (x iterations plus the per-core set-up), about target_wg workgroups in all and at most
 // kRingMaxPartialBytes of partial sums; fills bounds ([i1][nchunk + 1]) and, if asked for, the

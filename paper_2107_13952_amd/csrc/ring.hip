@@ -574,11 +574,15 @@ __global__ __launch_bounds__(RT, (ring_waves<DI, DK, KW>())) void ring_batch_ker
   for (;;) {
     if (threadIdx.x == 0) it_s = atomicAdd(next, 1);
     __syncthreads();
-    const int it = it_s;
+    // The item and its fields are the same for the whole workgroup: read them through scalar
+    // registers, so that the configuration's parameters are scalar loads too.
+    const int it = __builtin_amdgcn_readfirstlane(it_s);
     __syncthreads();
     if (it >= nitems) break;
     const int *p = items + 4 * it;
-    ring_item<DI, DK, KW, STG>(cfgs[p[0]], p[1], p[2], p[3], smem);
+    const int q0 = __builtin_amdgcn_readfirstlane(p[0]), q1 = __builtin_amdgcn_readfirstlane(p[1]);
+    const int q2 = __builtin_amdgcn_readfirstlane(p[2]), q3 = __builtin_amdgcn_readfirstlane(p[3]);
+    ring_item<DI, DK, KW, STG>(cfgs[q0], q1, q2, q3, smem);
   }
 }
 

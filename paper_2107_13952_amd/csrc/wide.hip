@@ -45,10 +45,12 @@ __device__ __forceinline__ d4v mfma(double a, double b, d4v c) {
 // LDS geometry of one configuration (all sizes in doubles).
 struct WideGeom {
   int R, C, RT, CT, RTb, GS, HS;
-  int t5, t2, g, h, meta;  // offsets
+  int t5, t2, g, h, mb, meta;  // offsets
 };
 
-__host__ __device__ inline WideGeom wide_geom(int nd, const int *i_n, int kw, int nrb) {
+// stg: the core's four weighted booster blocks are staged in LDS (16 x 16 each per spin value,
+// zero outside the block) for the operands of T5 / T2 and G / H.
+__host__ __device__ inline WideGeom wide_geom(int nd, const int *i_n, int kw, int nrb, bool stg) {
   WideGeom w;
   w.R = i_n[4] * i_n[3];
   w.C = i_n[2] * i_n[1];
@@ -61,24 +63,26 @@ __host__ __device__ inline WideGeom wide_geom(int nd, const int *i_n, int kw, in
   w.t2 = w.t5 + nd * 256;
   w.g = w.t2 + nd * 256;
   w.h = w.g + w.RTb * 16 * w.GS;
-  w.meta = w.h + kw * w.HS;
+  w.mb = w.h + kw * w.HS;
+  w.meta = w.mb + (stg ? 4 * nd * 256 : 0);
   return w;
 }
 
 // Bytes of LDS: the double buffers plus the per-core range table (8 ints per spin value) and
 // booster offsets (4 int64 per spin value).
-__host__ __device__ inline size_t wide_bytes(int nd, const int *i_n, int kw, int nrb) {
-  const WideGeom w = wide_geom(nd, i_n, kw, nrb);
+__host__ __device__ inline size_t wide_bytes(int nd, const int *i_n, int kw, int nrb, bool stg) {
+  const WideGeom w = wide_geom(nd, i_n, kw, nrb, stg);
   return sizeof(double) * (size_t)w.meta + sizeof(int) * 8 * (size_t)nd + sizeof(int64_t) * 4 * (size_t)nd;
 }
 
 // One work item: cores [bounds[i1][chunk], bounds[i1][chunk + 1]) of rp, boundary intertwiner
 // i1 = n1, row block rb of A(i1; rho, sig).
+template <bool STG>
 __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb, double *smem) {
   const int nd = rp.nd, nd3 = nd * nd * nd;
   const int d1 = rp.i_n[0], d2 = rp.i_n[1], d3 = rp.i_n[2], d4 = rp.i_n[3], d5 = rp.i_n[4];
   const int KW = rp.kw;
-  const WideGeom geo = wide_geom(nd, rp.i_n, KW, rp.nrb);
+  const WideGeom geo = wide_geom(nd, rp.i_n, KW, rp.nrb, STG);
   const int rt0 = rb * geo.RTb;
   const int rtn = imin(geo.RTb, geo.RT - rt0);  // row tiles of this block
   if (rtn <= 0) return;                          // uniform over the workgroup
@@ -89,10 +93,15 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
   double *T2s = smem + geo.t2;    // [l23][i2][k3 - lo3(l23)]
   double *Gs = smem + geo.g;      // [rho - rho0][k4 position], then P: [rho - rho0][k3 position]
   double *Hs = smem + geo.h;      // [k3 position][sig]
+  double *Mb = smem + geo.mb;     // [slot: M5, M4, M2, M3][spin value][i][k - lo], when STG
   int *rng = reinterpret_cast<int *>(smem + geo.meta);             // [8][nd]
   int64_t *bo = reinterpret_cast<int64_t *>(rng + 8 * nd);         // [4][nd]
 
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
+  // The wavefront index read through a scalar register, so that branches on it are uniform.
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4,
+            c = l & 15;
+  const int ntw = (ntile - w + WW - 1) / WW;  // accumulator tiles held by this wavefront
+  const int rt0w = w / CT, ct0w = w - rt0w * CT;  // its first tile
   const int *J = rp.two_j;
   const int two_i1 = rp.i_lo2[0] + 2 * n1;
   const int NX = rp.NX, nK2 = rp.K_n[0], nK3 = rp.K_n[1], nK4 = rp.K_n[2], nK5 = rp.K_n[3];
@@ -135,6 +144,19 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
       bo[3 * nd + o] = rp.boff[1 * nd3 + t3];  // M3
     }
     __syncthreads();
+    if (STG) {
+      // Weighted booster blocks (2k+1) B of this core, zero outside each block.
+      for (int q = tid; q < 4 * nd * 256; q += WT) {
+        const int slot = q / (nd * 256), o = (q >> 8) % nd, i = (q >> 4) & 15, k = q & 15;
+        const int ri = slot == 0 ? 0 : slot == 1 ? 2 : slot == 2 ? 4 : 6;
+        const int lo = rng[ri * nd + o], n = rng[(ri + 1) * nd + o];
+        const int di = slot == 0 ? d5 : slot == 1 ? d4 : slot == 2 ? d2 : d3;
+        double v = 0.0;
+        if (i < di && k < n) v = B[bo[slot * nd + o] + (int64_t)i * n + k] * (double)(lo + 2 * k + 1);
+        Mb[q] = v;
+      }
+      // (read after the x loop's first barrier)
+    }
     // Core windows of k4 (over l45) and of k3 (over l23).
     int w4lo = 1 << 30, w4hi = -1, w3lo = 1 << 30, w3hi = -1;
     for (int o = 0; o < nd; ++o) {
@@ -166,98 +188,106 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
       __syncthreads();  // previous x's readers of T5s / T2s / Gs / Hs are done
 
       // ---- T5 (per l45) and T2 (per l23): 16x16 tiles, K over the k5 (k2) values active at x.
+      // A operand: the booster block M5 (M2) of that spin, row c; B operand: the product of the
+      // two 6j columns, column c the k4 (k3) of that spin's range.  All loads of a task are issued
+      // before its multiply-adds (addresses clamped into range, values masked afterwards).
       for (int u = w; u < 2 * nd; u += WW) {
-        const int o = u < nd ? u : u - nd;
+        const bool s5 = u < nd;
+        const int o = s5 ? u : u - nd;
+        const int lo = rng[(s5 ? 0 : 4) * nd + o], n = rng[(s5 ? 1 : 5) * nd + o];
+        const int lop = rng[(s5 ? 2 : 6) * nd + o], np = rng[(s5 ? 3 : 7) * nd + o];
+        const int jq = s5 ? J[L14] : J[L13];
+        const int ka = imax(lo, iabs(x - jq)), kb = imin(lo + 2 * (n - 1), x + jq);
         d4v t = d4v{0.0, 0.0, 0.0, 0.0};
-        if (u < nd) {
-          const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
-          const int ka = imax(lo5, iabs(x - J[L14])), kb = imin(lo5 + 2 * (n5 - 1), x + J[L14]);
-          const int ia = (ka - lo5) >> 1, ib = (kb - lo5) >> 1;  // empty when kb < ka
-          const int64_t bm = bo[0 * nd + o];
-          const int k4g = (lo4 + 2 * c - rp.K_lo2[2]) >> 1;
-          const double *u1 = rp.U1 + (((int64_t)o25 * NX + xg) * d1 + n1) * nK5;
-          const double *u2 = rp.U2 + (((int64_t)o35 * nd + o) * NX + xg) * nK5 * nK4 + k4g;
-          for (int kk = ia & ~3; kb >= ka && kk <= ib; kk += 4) {
-            const int ki = kk + g;
+        if (kb >= ka) {  // uniform
+          const int ia = (ka - lo) >> 1, ib = (kb - lo) >> 1, kk0 = ia & ~3;
+          const bool rowok = c < (s5 ? d5 : d2), colok = c < np;
+          const int cr = rowok ? c : 0, cc = colok ? c : 0;
+          const double *bm = B + bo[(s5 ? 0 : 2) * nd + o] + (int64_t)cr * n;
+          const double *P, *Q;
+          int sP, sQ, kgb;
+          if (s5) {
+            kgb = (lo - rp.K_lo2[3]) >> 1;
+            P = rp.U1 + (((int64_t)o25 * NX + xg) * d1 + n1) * nK5;
+            Q = rp.U2 + (((int64_t)o35 * nd + o) * NX + xg) * nK5 * nK4 + ((lop + 2 * cc - rp.K_lo2[2]) >> 1);
+            sP = 1;
+            sQ = nK4;
+          } else {
+            kgb = (lo - rp.K_lo2[0]) >> 1;
+            P = rp.U5 + ((int64_t)o25 * NX + xg) * nK2 * d1 + n1;
+            Q = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + ((lop + 2 * cc - rp.K_lo2[1]) >> 1)) * nK2;
+            sP = d1;
+            sQ = 1;
+          }
+          constexpr int TS = 5;  // k steps of 4 covering at most 16 active values
+          double av[TS], bv[TS];
+#pragma unroll
+          for (int s = 0; s < TS; ++s) {
+            const int ki = kk0 + 4 * s + g;
             const bool kin = ki >= ia && ki <= ib;
-            const int k5 = lo5 + 2 * ki, k5g = (k5 - rp.K_lo2[3]) >> 1;
-            const double a = (kin && c < d5) ? B[bm + (int64_t)c * n5 + ki] * (double)(k5 + 1) : 0.0;
-            const double b = (kin && c < n4) ? u1[k5g] * u2[(int64_t)k5g * nK4] : 0.0;
-            t = mfma(a, b, t);
+            const int kc = kin ? ki : ia;
+            const double a = STG ? Mb[((s5 ? 0 : 2) * nd + o) * 256 + cr * 16 + kc]
+                                 : bm[kc] * (double)(lo + 2 * kc + 1);
+            const double b = P[(int64_t)(kgb + kc) * sP] * Q[(int64_t)(kgb + kc) * sQ];
+            av[s] = (kin && rowok) ? a : 0.0;
+            bv[s] = (kin && colok) ? b : 0.0;
           }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) T5s[(o * 16 + g + 4 * r) * 16 + c] = t[r];
-        } else {
-          const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
-          const int ka = imax(lo2, iabs(J[L13] - x)), kb = imin(lo2 + 2 * (n2 - 1), J[L13] + x);
-          const int ia = (ka - lo2) >> 1, ib = (kb - lo2) >> 1;
-          const int64_t bm = bo[2 * nd + o];
-          const int k3g = (lo3 + 2 * c - rp.K_lo2[1]) >> 1;
-          const double *u5 = rp.U5 + ((int64_t)o25 * NX + xg) * nK2 * d1 + n1;
-          const double *u4 = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g) * nK2;
-          for (int kk = ia & ~3; kb >= ka && kk <= ib; kk += 4) {
-            const int ki = kk + g;
-            const bool kin = ki >= ia && ki <= ib;
-            const int k2 = lo2 + 2 * ki, k2g = (k2 - rp.K_lo2[0]) >> 1;
-            const double a = (kin && c < d2) ? B[bm + (int64_t)c * n2 + ki] * (double)(k2 + 1) : 0.0;
-            const double b = (kin && c < n3) ? u5[(int64_t)k2g * d1] * u4[k2g] : 0.0;
-            t = mfma(a, b, t);
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) T2s[(o * 16 + g + 4 * r) * 16 + c] = t[r];
+          for (int s = 0; s < TS; ++s)
+            if (kk0 + 4 * s <= ib) t = mfma(av[s], bv[s], t);
         }
+        double *Ts = s5 ? T5s : T2s;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ts[(o * 16 + g + 4 * r) * 16 + c] = t[r];
       }
       __syncthreads();
 
-      // ---- G (per k4 position) and H (per k3 position): 16x16 tiles, K over l45 (l23).
+      // ---- G (per k4 position) and H (per k3 position): 16x16 tiles, K over l45 (l23), whose
+      // spin values sit in at most three groups of four.
       const int g0 = a4l & ~3, nG = (b4l | 3) - g0 + 1;
       const int h0 = a3l & ~3, nH = (b3l | 3) - h0 + 1;
       for (int u = w; u < nG + nH; u += WW) {
-        if (u < nG) {
-          const int p = g0 + u, k4 = w4lo + 2 * p;
-          d4v t = d4v{0.0, 0.0, 0.0, 0.0};
-          if (p >= a4l && p <= b4l) {
-            for (int kk = 0; kk < nd; kk += 4) {
-              const int o = kk + g;
-              bool ok = false;
-              int k4i = 0, n4 = 0;
-              if (o < nd) {
-                const int lo4 = rng[2 * nd + o];
-                n4 = rng[3 * nd + o];
-                k4i = (k4 - lo4) >> 1;
-                ok = n4 > 0 && k4 >= lo4 && k4i < n4;
-              }
-              const double a = ok ? T5s[(o * 16 + c) * 16 + k4i] : 0.0;
-              const double b = (ok && c < d4) ? B[bo[1 * nd + o] + (int64_t)c * n4 + k4i] * (double)(k4 + 1) : 0.0;
-              t = mfma(a, b, t);
-            }
+        const bool sg = u < nG;
+        const int p = sg ? g0 + u : h0 + u - nG;
+        const int wlo = sg ? w4lo : w3lo;
+        const int kv = wlo + 2 * p;
+        d4v t = d4v{0.0, 0.0, 0.0, 0.0};
+        if (sg ? (p >= a4l && p <= b4l) : (p >= a3l && p <= b3l)) {  // uniform
+          const int rlo = sg ? 2 : 6, mslot = sg ? 1 : 3;
+          const bool cin = c < (sg ? d4 : d3);
+          const int cm = cin ? c : 0;
+          constexpr int GS3 = 3;  // kWideMaxNd <= 12
+          double av[GS3], bv[GS3];
+#pragma unroll
+          for (int s = 0; s < GS3; ++s) {
+            const int o = 4 * s + g;
+            const int oc = o < nd ? o : 0;
+            const int lok = rng[rlo * nd + oc], nk = rng[(rlo + 1) * nd + oc];
+            const int ki = (kv - lok) >> 1;
+            const bool ok = o < nd && nk > 0 && kv >= lok && ki < nk;
+            const int kc = ok ? ki : 0;
+            const double tv = (sg ? T5s : T2s)[(oc * 16 + c) * 16 + kc];
+            // An empty block's offset may be the end of the booster buffer: read its start then.
+            const double *mp = ok ? B + bo[mslot * nd + oc] + (int64_t)cm * nk + kc : B;
+            const double mv = STG ? Mb[(mslot * nd + oc) * 256 + cm * 16 + kc] : *mp * (double)(kv + 1);
+            // G: A = T5 (rows i5), B = M4 (columns i4); H: A = M3 (rows i3), B = T2 (columns i2).
+            const double x1 = ok ? tv : 0.0, x2 = (ok && cin) ? mv : 0.0;
+            av[s] = sg ? x1 : x2;
+            bv[s] = sg ? x2 : x1;
           }
-          // rows i5 = 4g + r, column i4 = c  ->  rho = i5 d4 + i4
+#pragma unroll
+          for (int s = 0; s < GS3; ++s)
+            if (4 * s < nd) t = mfma(av[s], bv[s], t);
+        }
+        if (sg) {
+          // rows i5 = g + 4r, column i4 = c  ->  rho = i5 d4 + i4
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int rho = (g + 4 * r) * d4 + c - rho0;
             if (g + 4 * r < d5 && c < d4 && rho >= 0 && rho < nrow) Gs[rho * GS + p] = t[r];
           }
         } else {
-          const int p = h0 + u - nG, k3 = w3lo + 2 * p;
-          d4v t = d4v{0.0, 0.0, 0.0, 0.0};
-          if (p >= a3l && p <= b3l) {
-            for (int kk = 0; kk < nd; kk += 4) {
-              const int o = kk + g;
-              bool ok = false;
-              int k3i = 0, n3 = 0;
-              if (o < nd) {
-                const int lo3 = rng[6 * nd + o];
-                n3 = rng[7 * nd + o];
-                k3i = (k3 - lo3) >> 1;
-                ok = n3 > 0 && k3 >= lo3 && k3i < n3;
-              }
-              const double a = (ok && c < d3) ? B[bo[3 * nd + o] + (int64_t)c * n3 + k3i] * (double)(k3 + 1) : 0.0;
-              const double b = ok ? T2s[(o * 16 + c) * 16 + k3i] : 0.0;
-              t = mfma(a, b, t);
-            }
-          }
-          // rows i3 = 4g + r, column i2 = c  ->  sig = i3 d2 + i2
+          // rows i3 = g + 4r, column i2 = c  ->  sig = i3 d2 + i2
 #pragma unroll
           for (int r = 0; r < 4; ++r)
             if (g + 4 * r < d3 && c < d2) Hs[p * HS + (g + 4 * r) * d2 + c] = t[r];
@@ -266,22 +296,32 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
       __syncthreads();
 
       // ---- P = G U3 for the block's rows, written over G row tile by row tile (a wavefront
-      // reads and writes only its own row tiles, and finishes reading before it writes).
+      // reads and writes only its own row tiles, and finishes reading before it writes).  The
+      // operands of four k4 steps are loaded before their multiply-adds.
       const int nq = ((b3l | 3) + 16) / 16;  // k3 column tiles (1 or 2)
+      const double *u3row = rp.U3 + (u3base + xg) * nK4 * nK3 + ((w3lo - rp.K_lo2[1]) >> 1);
+      const int k4g0 = (w4lo - rp.K_lo2[2]) >> 1;
       for (int rt = w; rt < rtn; rt += WW) {
         d4v pq0 = d4v{0.0, 0.0, 0.0, 0.0}, pq1 = d4v{0.0, 0.0, 0.0, 0.0};
-        for (int ks = g0; ks <= b4l; ks += 4) {
-          const int kp = ks + g;
-          const double a = Gs[(rt * 16 + c) * GS + kp];
-          const bool kin = kp >= a4l && kp <= b4l;
-          const int k4g = (w4lo + 2 * kp - rp.K_lo2[2]) >> 1;
-          const double *u3 = rp.U3 + ((u3base + xg) * nK4 + k4g) * nK3 + ((w3lo - rp.K_lo2[1]) >> 1);
-          const int q0 = c, q1 = 16 + c;
-          const double b0 = (kin && q0 >= a3l && q0 <= b3l) ? u3[q0] : 0.0;
-          pq0 = mfma(a, b0, pq0);
-          if (nq > 1) {
-            const double b1 = (kin && q1 >= a3l && q1 <= b3l) ? u3[q1] : 0.0;
-            pq1 = mfma(a, b1, pq1);
+        for (int ks = g0; ks <= b4l; ks += 16) {
+          double av[4], b0[4], b1[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int kp = ks + 4 * s + g;
+            const bool kin = kp >= a4l && kp <= b4l;
+            const int kpc = kin ? kp : a4l;
+            av[s] = Gs[(rt * 16 + c) * GS + (kp < KW ? kp : KW - 1)];
+            const double *u3 = u3row + (int64_t)(k4g0 + kpc) * nK3;
+            const bool q0 = kin && c >= a3l && c <= b3l, q1 = kin && 16 + c >= a3l && 16 + c <= b3l;
+            const double v0 = u3[q0 ? c : a3l], v1 = u3[q1 ? 16 + c : a3l];
+            b0[s] = q0 ? v0 : 0.0;
+            b1[s] = q1 ? v1 : 0.0;
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            if (ks + 4 * s > b4l) break;  // uniform
+            pq0 = mfma(av[s], b0[s], pq0);
+            if (nq > 1) pq1 = mfma(av[s], b1[s], pq1);
           }
         }
         // Columns up to KW - 1 only: a row of G / P holds KW positions (the A update reads no
@@ -294,16 +334,32 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
       }
       __syncthreads();
 
-      // ---- A(i1; rho, sig) += P H over the active k3 positions.
+      // ---- A(i1; rho, sig) += P H over the active k3 positions.  This wavefront's tiles are
+      // t = w + 8 j, j < ntw, walked in order from (rt0, ct0) without divisions; per k step the
+      // operands of half of them are read from LDS before their multiply-adds.
+      const double *pa = Gs + c * GS + g, *pb = Hs + g * HS + c;  // this lane's parts of both operands
       for (int ks = h0; ks <= b3l; ks += 4) {
+        int rt = rt0w, ct = ct0w;
 #pragma unroll
-        for (int j = 0; j < kMaxAcc; ++j) {
-          const int t = w + WW * j;
-          if (t < ntile) {
-            const int rt = t / CT, ct = t - rt * CT;
-            const double a = Gs[(rt * 16 + c) * GS + ks + g];
-            const double b = Hs[(ks + g) * HS + ct * 16 + c];
-            acc[j] = mfma(a, b, acc[j]);
+        for (int half = 0; half < 2; ++half) {
+          double av[kMaxAcc / 2], bv[kMaxAcc / 2];
+#pragma unroll
+          for (int jj = 0; jj < kMaxAcc / 2; ++jj) {
+            const int j = half * (kMaxAcc / 2) + jj;
+            if (j < ntw) {
+              av[jj] = pa[rt * 16 * GS + ks];
+              bv[jj] = pb[ks * HS + ct * 16];
+              ct += WW;
+              while (ct >= CT) {
+                ct -= CT;
+                ++rt;
+              }
+            }
+          }
+#pragma unroll
+          for (int jj = 0; jj < kMaxAcc / 2; ++jj) {
+            const int j = half * (kMaxAcc / 2) + jj;
+            if (j < ntw) acc[j] = mfma(av[jj], bv[jj], acc[j]);
           }
         }
       }
@@ -330,15 +386,17 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
   __syncthreads();  // the next item reuses the LDS
 }
 
+template <bool STG>
 __global__ __launch_bounds__(WT, 1) void wide_kernel(RingParams rp) {
   extern __shared__ double smem[];
-  wide_item(rp, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+  wide_item<STG>(rp, blockIdx.x, blockIdx.y, blockIdx.z, smem);
 }
 
 // Persistent variant for batches: workgroups take (configuration, chunk, i1, row block) items of
 // a longest-first list from a counter; every item writes its own partial slice, so which
 // workgroup runs it does not matter.  The loop ends for every workgroup once the counter
 // passes nitems.
+template <bool STG>
 __global__ __launch_bounds__(WT, 1) void wide_batch_kernel(const RingParams *cfgs, const int *items,
                                                           int nitems, int *next) {
   extern __shared__ double smem[];
@@ -346,17 +404,23 @@ __global__ __launch_bounds__(WT, 1) void wide_batch_kernel(const RingParams *cfg
   for (;;) {
     if (threadIdx.x == 0) it_s = atomicAdd(next, 1);
     __syncthreads();
-    const int it = it_s;
+    // The item and its fields are the same for the whole workgroup: read them through scalar
+    // registers, so that the configuration's parameters are scalar loads too.
+    const int it = __builtin_amdgcn_readfirstlane(it_s);
     __syncthreads();
     if (it >= nitems) break;
     const int *p = items + 4 * it;
-    wide_item(cfgs[p[0]], p[1], p[2], p[3], smem);
+    const int q0 = __builtin_amdgcn_readfirstlane(p[0]), q1 = __builtin_amdgcn_readfirstlane(p[1]);
+    const int q2 = __builtin_amdgcn_readfirstlane(p[2]), q3 = __builtin_amdgcn_readfirstlane(p[3]);
+    wide_item<STG>(cfgs[q0], q1, q2, q3, smem);
   }
 }
 
 }  // namespace
 
-size_t wide_smem_bytes(int nd, const int i_n[5], int kw, int nrb) { return wide_bytes(nd, i_n, kw, nrb); }
+size_t wide_smem_bytes(int nd, const int i_n[5], int kw, int nrb, bool stg) {
+  return wide_bytes(nd, i_n, kw, nrb, stg);
+}
 
 int wide_row_blocks(const int i_n[5]) {
   const int RT = (i_n[4] * i_n[3] + 15) / 16, CT = (i_n[2] * i_n[1] + 15) / 16;
@@ -365,28 +429,37 @@ int wide_row_blocks(const int i_n[5]) {
   return 0;  // a single row tile already needs more accumulators than a workgroup holds
 }
 
-bool wide_fits(int nd, const int i_n[5], int kw, int nrb) {
-  return nrb > 0 && kw <= 32 && wide_bytes(nd, i_n, kw, nrb) <= kLdsBytes - 256;
+bool wide_fits(int nd, const int i_n[5], int kw, int nrb, bool stg) {
+  return nrb > 0 && kw <= 32 && wide_bytes(nd, i_n, kw, nrb, stg) <= kLdsBytes - 256;
 }
 
 hipError_t wide_init_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void *)wide_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - 256));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)wide_batch_kernel,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - 256));
+  const int bytes = (int)(kLdsBytes - 256);
+  const void *fns[4] = {(const void *)wide_kernel<false>, (const void *)wide_kernel<true>,
+                        (const void *)wide_batch_kernel<false>, (const void *)wide_batch_kernel<true>};
+  for (const void *f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_wide(const RingParams &rp, hipStream_t s) {
   dim3 grid(rp.nchunk, rp.i_n[0], rp.nrb);
-  wide_kernel<<<grid, WT, wide_bytes(rp.nd, rp.i_n, rp.kw, rp.nrb), s>>>(rp);
+  if (wide_fits(rp.nd, rp.i_n, rp.kw, rp.nrb, true))
+    wide_kernel<true><<<grid, WT, wide_bytes(rp.nd, rp.i_n, rp.kw, rp.nrb, true), s>>>(rp);
+  else
+    wide_kernel<false><<<grid, WT, wide_bytes(rp.nd, rp.i_n, rp.kw, rp.nrb, false), s>>>(rp);
   return hipGetLastError();
 }
 
 hipError_t launch_wide_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems,
-                             size_t smem, int grid, int *next, hipStream_t s) {
+                             size_t smem, bool stg, int grid, int *next, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  wide_batch_kernel<<<grid, WT, smem, s>>>(cfgs_dev, items_dev, nitems, next);
+  if (stg)
+    wide_batch_kernel<true><<<grid, WT, smem, s>>>(cfgs_dev, items_dev, nitems, next);
+  else
+    wide_batch_kernel<false><<<grid, WT, smem, s>>>(cfgs_dev, items_dev, nitems, next);
   return hipGetLastError();
 }
 
