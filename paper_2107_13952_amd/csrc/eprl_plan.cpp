@@ -232,7 +232,13 @@ int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds,
   const int xlo_g = p.X.lo2, xhi_g = p.X.lo2 + 2 * (p.X.n - 1);
   std::vector<double> cost((size_t)d1 * ncore, 0.0);
   for (int core = 0; core < ncore; ++core) {
-    const int o24 = core / nd3, o25 = (core / (nd * nd)) % nd, o34 = (core / nd) % nd, o35 = core % nd;
+    // Core order of the kernel: (l24, l25, l34, l35) with l35 fastest, or for the wide kernel
+    // (l24, l34, l35, l25) with l25 fastest.
+    const bool wide = p.ring_cls == kWideClass;
+    const int o24 = core / nd3;
+    const int o25 = wide ? core % nd : (core / (nd * nd)) % nd;
+    const int o34 = wide ? (core / (nd * nd)) % nd : (core / nd) % nd;
+    const int o35 = wide ? (core / nd) % nd : core % nd;
     // Windows of k4 over l45 and of k3 over l23 (pairs with an empty range left out), as the
     // kernel forms them.
     int w4lo = 1 << 30, w4hi = -1, w3lo = 1 << 30, w3hi = -1;

@@ -119,7 +119,9 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
   const int c0 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index];
   const int c1 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index + 1];
   for (int core = c0; core < c1; ++core) {
-    const int o24 = core / nd3, o25 = (core / (nd * nd)) % nd, o34 = (core / nd) % nd, o35 = core % nd;
+    // Cores run with l25 fastest: consecutive cores of a chunk then share the U2, U3, U4 slices
+    // and the M4, M3 blocks (none depends on l25), which stay in the caches.
+    const int o24 = core / nd3, o34 = (core / (nd * nd)) % nd, o35 = (core / nd) % nd, o25 = core % nd;
     const int l24 = J[L24] + 2 * o24, l25 = J[L25] + 2 * o25, l35 = J[L35] + 2 * o35;
     __syncthreads();  // previous readers of rng / bo (and of the LDS tiles) are done
     for (int o = tid; o < nd; o += WT) {
@@ -243,54 +245,67 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
       __syncthreads();
 
       // ---- G (per k4 position) and H (per k3 position): 16x16 tiles, K over l45 (l23), whose
-      // spin values sit in at most three groups of four.
-      const int g0 = a4l & ~3, nG = (b4l | 3) - g0 + 1;
+      // spin values sit in at most three groups of four.  A task takes four consecutive positions
+      // of G or of H, sharing the spin ranges it looks up.
+      const int g0 = a4l & ~3, nG = (b4l | 3) - g0 + 1;  // multiples of 4
       const int h0 = a3l & ~3, nH = (b3l | 3) - h0 + 1;
-      for (int u = w; u < nG + nH; u += WW) {
-        const bool sg = u < nG;
-        const int p = sg ? g0 + u : h0 + u - nG;
+      for (int u = w; u < (nG + nH) / 4; u += WW) {
+        const bool sg = u < nG / 4;
+        const int p0 = sg ? g0 + 4 * u : h0 + 4 * u - nG;
         const int wlo = sg ? w4lo : w3lo;
-        const int kv = wlo + 2 * p;
-        d4v t = d4v{0.0, 0.0, 0.0, 0.0};
-        if (sg ? (p >= a4l && p <= b4l) : (p >= a3l && p <= b3l)) {  // uniform
-          const int rlo = sg ? 2 : 6, mslot = sg ? 1 : 3;
-          const bool cin = c < (sg ? d4 : d3);
-          const int cm = cin ? c : 0;
-          constexpr int GS3 = 3;  // kWideMaxNd <= 12
-          double av[GS3], bv[GS3];
+        const int pa = sg ? a4l : a3l, pb = sg ? b4l : b3l;
+        const int rlo = sg ? 2 : 6, mslot = sg ? 1 : 3;
+        const bool cin = c < (sg ? d4 : d3);
+        const int cm = cin ? c : 0;
+        const double *Ts = sg ? T5s : T2s;
+        constexpr int GS3 = 3;  // kWideMaxNd <= 12
+        int lok[GS3], nk[GS3], oc[GS3];
+        bool ov[GS3];
 #pragma unroll
-          for (int s = 0; s < GS3; ++s) {
-            const int o = 4 * s + g;
-            const int oc = o < nd ? o : 0;
-            const int lok = rng[rlo * nd + oc], nk = rng[(rlo + 1) * nd + oc];
-            const int ki = (kv - lok) >> 1;
-            const bool ok = o < nd && nk > 0 && kv >= lok && ki < nk;
-            const int kc = ok ? ki : 0;
-            const double tv = (sg ? T5s : T2s)[(oc * 16 + c) * 16 + kc];
-            // An empty block's offset may be the end of the booster buffer: read its start then.
-            const double *mp = ok ? B + bo[mslot * nd + oc] + (int64_t)cm * nk + kc : B;
-            const double mv = STG ? Mb[(mslot * nd + oc) * 256 + cm * 16 + kc] : *mp * (double)(kv + 1);
-            // G: A = T5 (rows i5), B = M4 (columns i4); H: A = M3 (rows i3), B = T2 (columns i2).
-            const double x1 = ok ? tv : 0.0, x2 = (ok && cin) ? mv : 0.0;
-            av[s] = sg ? x1 : x2;
-            bv[s] = sg ? x2 : x1;
-          }
-#pragma unroll
-          for (int s = 0; s < GS3; ++s)
-            if (4 * s < nd) t = mfma(av[s], bv[s], t);
+        for (int s = 0; s < GS3; ++s) {
+          const int o = 4 * s + g;
+          ov[s] = o < nd;
+          oc[s] = ov[s] ? o : 0;
+          lok[s] = rng[rlo * nd + oc[s]];
+          nk[s] = rng[(rlo + 1) * nd + oc[s]];
         }
-        if (sg) {
-          // rows i5 = g + 4r, column i4 = c  ->  rho = i5 d4 + i4
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int rho = (g + 4 * r) * d4 + c - rho0;
-            if (g + 4 * r < d5 && c < d4 && rho >= 0 && rho < nrow) Gs[rho * GS + p] = t[r];
+        for (int pi = 0; pi < 4; ++pi) {
+          const int p = p0 + pi, kv = wlo + 2 * p;
+          d4v t = d4v{0.0, 0.0, 0.0, 0.0};
+          if (p >= pa && p <= pb) {  // uniform
+            double av[GS3], bv[GS3];
+#pragma unroll
+            for (int s = 0; s < GS3; ++s) {
+              const int ki = (kv - lok[s]) >> 1;
+              const bool ok = ov[s] && nk[s] > 0 && kv >= lok[s] && ki < nk[s];
+              const int kc = ok ? ki : 0;
+              const double tv = Ts[(oc[s] * 16 + c) * 16 + kc];
+              // An empty block's offset may be the end of the booster buffer: read its start then.
+              const double *mp = ok ? B + bo[mslot * nd + oc[s]] + (int64_t)cm * nk[s] + kc : B;
+              const double mv = STG ? Mb[(mslot * nd + oc[s]) * 256 + cm * 16 + kc] : *mp * (double)(kv + 1);
+              // G: A = T5 (rows i5), B = M4 (columns i4); H: A = M3 (rows i3), B = T2 (columns i2).
+              const double x1 = ok ? tv : 0.0, x2 = (ok && cin) ? mv : 0.0;
+              av[s] = sg ? x1 : x2;
+              bv[s] = sg ? x2 : x1;
+            }
+#pragma unroll
+            for (int s = 0; s < GS3; ++s)
+              if (4 * s < nd) t = mfma(av[s], bv[s], t);
           }
-        } else {
-          // rows i3 = g + 4r, column i2 = c  ->  sig = i3 d2 + i2
+          if (sg) {
+            // rows i5 = g + 4r, column i4 = c  ->  rho = i5 d4 + i4
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (g + 4 * r < d3 && c < d2) Hs[p * HS + (g + 4 * r) * d2 + c] = t[r];
+            for (int r = 0; r < 4; ++r) {
+              const int rho = (g + 4 * r) * d4 + c - rho0;
+              if (g + 4 * r < d5 && c < d4 && rho >= 0 && rho < nrow) Gs[rho * GS + p] = t[r];
+            }
+          } else {
+            // rows i3 = g + 4r, column i2 = c  ->  sig = i3 d2 + i2
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (g + 4 * r < d3 && c < d2) Hs[p * HS + (g + 4 * r) * d2 + c] = t[r];
+          }
         }
       }
       __syncthreads();
