@@ -18,8 +18,8 @@ Prints one JSON line:
   cpu_baseline the CPU oracle timed on a bounded sample of the same workload, on every host core
   batched_vs_plain  forward only: the batched call against 16 plain calls (median of replays)
   Extra blocks: the equilateral j = 3, dl = 8 plain vertex (``plain_j3_dl8``), the 64-configuration
-  irregular batch (``irregular_batch``) and the j = 4, dl = 8 differentiation check
-  (``differentiation``).
+  irregular batch (``irregular_batch``), the j = 3 shell scan dl = 0..8 (``shell_scan_j3``) and
+  the j = 4, dl = 8 differentiation check (``differentiation``).
 """
 import argparse
 import hashlib
@@ -102,11 +102,11 @@ def quadrature_boosters(two_j, dl, size):
     return np.ascontiguousarray(g["boosters"], dtype=np.float64)
 
 
-def measured_traffic(name, key):
+def measured_traffic(name, key, source):
     """HBM bytes per launch of a kernel from a committed counter summary, when it was taken on
-    the current kernel source (same sha256 prefix) and names `key`; otherwise None."""
+    the current kernel source file `source` (same sha256 prefix) and names `key`; else None."""
     path = os.path.join(ROOT, "profiles", name)
-    src = os.path.join(ROOT, "paper_2107_13952_amd", "csrc", "ring.hip")
+    src = os.path.join(ROOT, "paper_2107_13952_amd", "csrc", source)
     try:
         text = open(path).read()
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -214,7 +214,7 @@ def plain_j3(lib, torch, dev, synthetic, autotune, steps):
                             "frac": work["ring_useful_flops"] / (ring_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                             "mfma_executed_tflops": work["ring_mfma_flops"] / (ring_ms * 1e-3) / 1e12,
                             "traffic": measured_traffic("ring_kernel_j3_dl8_counters.md",
-                                                        "traffic bytes per launch, split 8192 2")}}
+                                                        "traffic bytes per launch, split 8192 2", "ring.hip")}}
 
 
 def irregular_batch(lib, torch, dev, reps):
@@ -232,6 +232,33 @@ def irregular_batch(lib, torch, dev, reps):
             "batched_terms_per_s": terms / (statistics.median(tb) * 1e-3),
             "plain_terms_per_s": terms / (statistics.median(tp) * 1e-3),
             "batched": spread(tb), "plain": spread(tp)}
+
+
+def shell_scan(lib, torch, dev, reps):
+    """A(dl) for dl = 0..8 of the equilateral j = 3 vertex from one booster buffer packed for
+    dl = 8 (one batched call) against the nine plain calls on their own packed boosters."""
+    cfg = workloads.CFG2
+    two_j, dl_max = cfg["two_j"], cfg["dl"]
+    b = torch.from_numpy(workloads.synthetic_boosters(cfg["booster_seed"],
+                                                      block_shapes(lib, two_j, dl_max))).to(dev)
+    out = lib.vertex_tensor_scan(two_j, dl_max, 1.2, b)
+    # Per-dl buffers for the plain calls: the blocks of each dl taken out of the dl_max buffer.
+    _, _, offs = lib.layout(two_j, dl_max)
+    n3 = (dl_max + 1) ** 3
+    sub = []
+    for d in range(dl_max + 1):
+        idx = [e * n3 + (o1 * (dl_max + 1) + o2) * (dl_max + 1) + o3 for e in range(4)
+               for o1 in range(d + 1) for o2 in range(d + 1) for o3 in range(d + 1)]
+        sub.append(torch.cat([b[int(offs[q]):int(offs[q + 1])] for q in idx]))
+    terms = sum(lib.count_terms(two_j, d)[1] for d in range(dl_max + 1))
+    ts = event_times(torch, lambda: lib.vertex_tensor_scan(two_j, dl_max, 1.2, b, out=out), reps)
+    tp = event_times(torch, lambda: [lib.vertex_tensor(two_j, d, 1.2, sub[d], out=out[d])
+                                     for d in range(dl_max + 1)], reps)
+    return {"workload": "shell scan A(dl), dl = 0..8, equilateral j=3 (two_j=6), seeded boosters",
+            "terms": terms, "scan": spread(ts), "plain_calls": spread(tp),
+            "scan_terms_per_s": terms / (statistics.median(ts) * 1e-3),
+            "plain_terms_per_s": terms / (statistics.median(tp) * 1e-3),
+            "single_dl8_terms": lib.count_terms(two_j, dl_max)[1]}
 
 
 def differentiation(lib, torch, dev):
@@ -299,7 +326,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-shells", type=int, default=20,
+    ap.add_argument("--cpu-shells", type=int, default=400,
                     help="oracle shells per host core for the CPU baseline (0 = skip)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline step (no j=3 plain, irregular batch or j=4 blocks)")
@@ -383,7 +410,10 @@ def main():
     kernel_ms = kms / max(kn, 1)
     alg_per_launch = useful / max(launches, 1.0)
     achieved = alg_per_launch / (kernel_ms * 1e-3) / 1e12
-    progress(f"ring_batch_kernel {kernel_ms:.2f} ms per launch ({launches:g} launches per step): "
+    # Every configuration of this batch takes the all-matrix-core factorised kernel (class 8)
+    # unless the planner picked otherwise; the roofline names the kernel that ran.
+    kname, ksrc = ("wide_batch_kernel", "wide.hip") if classes == [8] else ("ring_batch_kernel", "ring.hip")
+    progress(f"{kname} {kernel_ms:.2f} ms per launch ({launches:g} launches per step): "
              f"{achieved:.2f} TFLOP/s useful")
 
     result = {
@@ -415,9 +445,9 @@ def main():
                              "contraction_and_adjoint": spread(fa)},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic("ring_batch_kernel_large_batch_counters.md",
-                                                 "traffic bytes per launch"),
-                     "kernel": "ring_batch_kernel", "avg_ms": kernel_ms,
+                     "traffic": measured_traffic(f"{kname}_large_batch_counters.md",
+                                                 "traffic bytes per launch", ksrc),
+                     "kernel": kname, "avg_ms": kernel_ms,
                      "launches_per_step": launches,
                      "alg_flops_per_launch": alg_per_launch,
                      "alg_flops_per_term": useful / lb.terms,
@@ -431,6 +461,8 @@ def main():
                                           not args.no_autotune, 10)
         progress("irregular batch")
         result["irregular_batch"] = irregular_batch(lib, torch, dev, 5)
+        progress("shell scan j=3 dl=0..8")
+        result["shell_scan_j3"] = shell_scan(lib, torch, dev, 5)
         progress("differentiation j=4 dl=8")
         result["differentiation"] = differentiation(lib, torch, dev)
     if cpu is not None:

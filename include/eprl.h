@@ -166,6 +166,20 @@ int eprl_vertex_tensor_range(eprl_ctx *ctx, const int two_j[10], int dl, double 
                              const double *boosters, int64_t shell_begin, int64_t shell_end,
                              int accumulate, double *A);
 
+/* Same, restricted to the shells of the "cores" [core_begin, core_end) in the factorised order
+ * (regrouping by linearity of the shell sum of eq. (vertex-ampl); the paper distributes shells
+ * over workers, Sec. 3.1 "Parallelization"): core index
+ *     ((o24 (dl+1) + o25) (dl+1) + o34) (dl+1) + o35,   o_ab = (l_ab - j_ab) in [0, dl],
+ * with every l23 and l45 of each core included.  accumulate = 0 overwrites A, 1 adds to it;
+ * consecutive core ranges reproduce the full tensor, and the range [0, (dl+1)^4) gives the same
+ * bits as eprl_vertex_tensor.  This is the resume / sharding unit of the factorised order (the
+ * shell-range call evaluates in the per-shell order).  EPRL_EINVAL for a range outside
+ * [0, (dl+1)^4] or when the per-shell order is forced; EPRL_ERANGE when the configuration has
+ * no factorised evaluation (intertwiner or k dimension above 16, core window above 32). */
+int eprl_vertex_tensor_cores(eprl_ctx *ctx, const int two_j[10], int dl, double gamma,
+                             const double *boosters, int64_t core_begin, int64_t core_end,
+                             int accumulate, double *A);
+
 /* n independent vertex tensors (configuration c: two_j[10 c .. 10 c + 9], dl[c],
  * boosters[c], A[c]); the host arrays of pointers hold device pointers.  The 6j tables, one
  * persistent launch per tile class over a longest-first work queue of all configurations and
@@ -173,6 +187,17 @@ int eprl_vertex_tensor_range(eprl_ctx *ctx, const int two_j[10], int dl, double 
  * and algorithm are unchanged.  Results are bitwise equal to n calls of eprl_vertex_tensor. */
 int eprl_vertex_tensor_batched(eprl_ctx *ctx, int n, const int *two_j, const int *dl,
                                double gamma, const double *const *boosters, double *const *A);
+
+/* Shell scan: the vertex tensors A(dl) for dl = 0, 1, ..., dl_max of one spin configuration, as
+ * needed for the convergence of the shell sum (Sec. 4.1 and the "EPRL vertex" study of Sec. 4.2:
+ * A(dl) = A(dl - 1) + the shells whose largest offset is dl).  boosters: device, packed for
+ * dl_max (eprl_layout(two_j, dl_max)); each A(dl) reads the blocks of its own shells from it.
+ * A: device, (dl_max + 1) prod(dims_i) doubles, A(dl) at offset dl prod(dims_i), overwritten.
+ * The dl_max + 1 tensors run as one batch (one graph of table builds, persistent launches and
+ * reductions; see eprl_vertex_tensor_batched): every A(dl) has the bits of
+ * eprl_vertex_tensor(two_j, dl) on its own packed boosters.  Errors as eprl_vertex_tensor. */
+int eprl_vertex_tensor_scan(eprl_ctx *ctx, const int two_j[10], int dl_max, double gamma,
+                            const double *boosters, double *A);
 
 /* Boundary contraction (Sec. 3.2, `contract`):
  *   F = sum_{i1..i5} A(i1..i5) psi1(i1) psi2(i2) psi3(i3) psi4(i4) psi5(i5)

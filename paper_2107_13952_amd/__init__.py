@@ -11,7 +11,9 @@ Functions mirror the C entry points:
 * ``vertex_tensor(two_j, dl, gamma, boosters)``          eq. (vertex-ampl)
 * ``bf_vertex_tensor(two_j)``                              the BF (15j) vertex, no boosters
 * ``vertex_tensor_range(...)``                            partial shell sums (resume unit)
+* ``vertex_tensor_cores(...)``                            partial sums over cores (l24, l25, l34, l35)
 * ``vertex_tensor_batched(configs, gamma, boosters)``     many configurations, one launch
+* ``vertex_tensor_scan(two_j, dl_max, gamma, boosters)``  A(dl) for dl = 0..dl_max, one batch
 * ``contract_boundary(A, psis)``                          contraction with five vectors
 * ``contract_boundary_adjoint(...)``                      its derivatives
 * ``VertexContract``                                      torch.autograd.Function of F(psi, B)
@@ -51,6 +53,9 @@ _SIGS = {
     "eprl_bf_vertex_tensor": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp]),
     "eprl_vertex_tensor_range": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_double, _dp,
                                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _dp]),
+    "eprl_vertex_tensor_cores": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_double, _dp,
+                                                ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _dp]),
+    "eprl_vertex_tensor_scan": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_double, _dp, _dp]),
     "eprl_vertex_tensor_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, ctypes.c_double,
                                                   ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
     "eprl_contract_boundary": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp, ctypes.POINTER(ctypes.c_void_p), _dp]),
@@ -211,7 +216,7 @@ def bf_vertex_tensor(two_j, device="cuda", out=None):
     return out
 
 
-def vertex_tensor_range(two_j, dl, gamma, boosters, shell_begin, shell_end, accumulate=False, out=None):
+def _partial_call(fn, two_j, dl, gamma, boosters, begin, end, accumulate, out):
     torch = _torch()
     dims, _, offs = _layout(tuple(int(v) for v in two_j), int(dl))
     dims = list(dims)
@@ -226,8 +231,40 @@ def vertex_tensor_range(two_j, dl, gamma, boosters, shell_begin, shell_end, accu
     if list(out.shape) != dims:
         raise ValueError(f"output shape {list(out.shape)} != {dims}")
     ctx = _ctx(boosters.device)
-    ctx.check(_lib.eprl_vertex_tensor_range(ctx.bind(), _ints(two_j, 10), int(dl), float(gamma), bp,
-                                            int(shell_begin), int(shell_end), 1 if accumulate else 0, ap))
+    ctx.check(fn(ctx.bind(), _ints(two_j, 10), int(dl), float(gamma), bp, int(begin), int(end),
+                 1 if accumulate else 0, ap))
+    return out
+
+
+def vertex_tensor_range(two_j, dl, gamma, boosters, shell_begin, shell_end, accumulate=False, out=None):
+    """Partial sum of A over shells [shell_begin, shell_end) of the (dl+1)^6 enumeration."""
+    return _partial_call(_lib.eprl_vertex_tensor_range, two_j, dl, gamma, boosters, shell_begin,
+                         shell_end, accumulate, out)
+
+
+def vertex_tensor_cores(two_j, dl, gamma, boosters, core_begin, core_end, accumulate=False, out=None):
+    """Partial sum of A over the cores [core_begin, core_end) of the factorised order, core
+    ((o24 (dl+1) + o25) (dl+1) + o34) (dl+1) + o35, every l23 and l45 included."""
+    return _partial_call(_lib.eprl_vertex_tensor_cores, two_j, dl, gamma, boosters, core_begin,
+                         core_end, accumulate, out)
+
+
+def vertex_tensor_scan(two_j, dl_max, gamma, boosters, out=None):
+    """A(dl) for dl = 0..dl_max as one float64 tensor [dl_max + 1, i1, .., i5]; boosters packed
+    for dl_max (layout(two_j, dl_max))."""
+    torch = _torch()
+    dims, _, offs = _layout(tuple(int(v) for v in two_j), int(dl_max))
+    shape = [int(dl_max) + 1] + list(dims)
+    if boosters.numel() != int(offs[-1]):
+        raise ValueError(f"booster buffer holds {boosters.numel()} values, layout needs {int(offs[-1])}")
+    bp = _check_dev(boosters, torch.float64, "boosters")
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=boosters.device)
+    ap = _check_dev(out, torch.float64, "out")
+    if list(out.shape) != shape:
+        raise ValueError(f"output shape {list(out.shape)} != {shape}")
+    ctx = _ctx(boosters.device)
+    ctx.check(_lib.eprl_vertex_tensor_scan(ctx.bind(), _ints(two_j, 10), int(dl_max), float(gamma), bp, ap))
     return out
 
 

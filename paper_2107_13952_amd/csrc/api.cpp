@@ -407,17 +407,20 @@ RingParams ring_params(const Prepared &prep, const double *B) {
   return rp;
 }
 
-// Factorised evaluation over all shells (one launch of the ring kernel, then the reduction).
+// Factorised evaluation over the cores [core_lo, core_hi) (core_hi < 0: all cores), every
+// l23 and l45 inside: one launch of the ring kernel, then the reduction.
 int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int accumulate,
-              double *A, const Plan &probe) {
+              double *A, const Plan &probe, int core_lo = 0, int core_hi = -1) {
   const int cls = probe.ring_cls;
   const int target = c->tune_wg[cls] > 0 ? c->tune_wg[cls] : kRingTargetWG;
   std::vector<int> key(two_j, two_j + 10);
   key.push_back(dl);
   key.push_back(target);
   key.push_back(cls);
+  key.push_back(core_lo);
+  key.push_back(core_hi);
   if (key != c->sched_key) {
-    c->sched_nchunk = ring_schedule(probe, target, c->sched_bounds);
+    c->sched_nchunk = ring_schedule(probe, target, c->sched_bounds, nullptr, core_lo, core_hi);
     c->sched_key = key;
   }
   const std::vector<int> &bounds = c->sched_bounds;
@@ -511,6 +514,31 @@ int vertex_range_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, co
   return EPRL_OK;
 }
 
+int vertex_cores_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, const double *B,
+                      int64_t cb, int64_t ce, int accumulate, double *A) {
+  if (!(gamma > 0.0) || !std::isfinite(gamma))
+    return fail(c, EPRL_EINVAL, "gamma must be finite and positive");
+  if (!B || !A) return fail(c, EPRL_EINVAL, "null booster or output pointer");
+  if (c->algo == EPRL_ALGO_SHELL)
+    return fail(c, EPRL_EINVAL, "core ranges are units of the factorised order, not of the per-shell order");
+  const Plan *pp = nullptr;
+  int rc = plan_for(c, two_j, dl, &pp);
+  if (rc) return rc;
+  const Plan &probe = *pp;
+  const int64_t ncore = (int64_t)probe.nd * probe.nd * probe.nd * probe.nd;
+  if (cb < 0 || ce > ncore || cb > ce)
+    return fail(c, EPRL_EINVAL, "core range outside [0, (dl+1)^4]");
+  if (probe.D == 0) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
+  if (probe.ring_KW == 0)
+    return fail(c, EPRL_ERANGE,
+                "the factorised path needs i and k ranges <= 16 and core windows <= 32");
+  if (c->algo == EPRL_ALGO_RING_VALU && probe.ring_cls != probe.ring_cls8) {
+    Plan q = probe;
+    q.ring_cls = q.ring_cls8;
+    return ring_impl(c, two_j, dl, B, accumulate, A, q, (int)cb, (int)ce);
+  }
+  return ring_impl(c, two_j, dl, B, accumulate, A, probe, (int)cb, (int)ce);
+}
 
 // ---- batched path ------------------------------------------------------------------------
 //
@@ -647,11 +675,17 @@ int run_batch(eprl_ctx *c) {
   return EPRL_OK;
 }
 
+// layout_dl (may be null): configuration q reads its boosters from a buffer packed for
+// layout_dl[q] >= dl[q] shells per link (the blocks of its own spins found by their offsets in
+// that larger layout).
 int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
-                 const double *const *boosters, double *const *A) {
+                 const double *const *boosters, double *const *A, const int *layout_dl = nullptr) {
   std::vector<int64_t> key;
   key.push_back(n);
   key.push_back(c->algo);
+  key.push_back(layout_dl != nullptr);
+  if (layout_dl)
+    for (int q = 0; q < n; ++q) key.push_back(layout_dl[q]);
   for (int q = 0; q < kRingClasses; ++q) {
     key.push_back(c->tune_wg[q]);
     key.push_back(c->tune_stg[q]);
@@ -676,6 +710,19 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
       std::ostringstream os;
       os << "configuration " << q << ": " << err;
       return fail(c, rc, os.str());
+    }
+    if (layout_dl && layout_dl[q] != dl[q]) {
+      Plan pl;
+      if (layout_dl[q] < dl[q]) return fail(c, EPRL_EINVAL, "booster layout smaller than the shells");
+      rc = make_plan(two_j + 10 * q, layout_dl[q], pl, err);
+      if (rc) return fail(c, rc, err);
+      const int nd = b.plan.nd, nd3 = nd * nd * nd, ndl = pl.nd, ndl3 = ndl * ndl * ndl;
+      for (int e = 0; e < 4; ++e)
+        for (int t = 0; t < nd3; ++t) {
+          const int tl = ((t / (nd * nd)) * ndl + (t / nd) % nd) * ndl + t % nd;
+          b.plan.boff[(size_t)e * nd3 + t] = pl.boff[(size_t)e * ndl3 + tl];
+        }
+      b.plan.boff[4 * (size_t)nd3] = pl.boff[4 * (size_t)ndl3];
     }
     const Plan &p = b.plan;
     if (p.D == 0) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
@@ -1089,6 +1136,13 @@ int eprl_vertex_tensor_range(eprl_ctx *c, const int two_j[10], int dl, double ga
   return vertex_range_impl(c, two_j, dl, gamma, B, shell_begin, shell_end, accumulate ? 1 : 0, A);
 }
 
+int eprl_vertex_tensor_cores(eprl_ctx *c, const int two_j[10], int dl, double gamma,
+                             const double *B, int64_t core_begin, int64_t core_end, int accumulate,
+                             double *A) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  return vertex_cores_impl(c, two_j, dl, gamma, B, core_begin, core_end, accumulate ? 1 : 0, A);
+}
+
 int eprl_vertex_tensor_batched(eprl_ctx *c, int n, const int *two_j, const int *dl, double gamma,
                                const double *const *boosters, double *const *A) {
   if (check_ctx(c)) return EPRL_EINVAL;
@@ -1098,6 +1152,29 @@ int eprl_vertex_tensor_batched(eprl_ctx *c, int n, const int *two_j, const int *
     return fail(c, EPRL_EINVAL, "gamma must be finite and positive");
   if (n == 0) return EPRL_OK;
   return batched_impl(c, n, two_j, dl, boosters, A);
+}
+
+int eprl_vertex_tensor_scan(eprl_ctx *c, const int two_j[10], int dl_max, double gamma,
+                            const double *B, double *A) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!(gamma > 0.0) || !std::isfinite(gamma))
+    return fail(c, EPRL_EINVAL, "gamma must be finite and positive");
+  if (!two_j || !B || !A) return fail(c, EPRL_EINVAL, "null argument");
+  if (dl_max < 0) return fail(c, EPRL_EINVAL, "dl_max must be >= 0");
+  const Plan *pp = nullptr;
+  int rc = plan_for(c, two_j, dl_max, &pp);
+  if (rc) return rc;
+  const int64_t a_size = pp->a_size;
+  const int n = dl_max + 1;
+  std::vector<int> tj((size_t)10 * n), dl(n), lay(n, dl_max);
+  std::vector<const double *> bp(n, B);
+  std::vector<double *> ap(n);
+  for (int d = 0; d < n; ++d) {
+    std::copy(two_j, two_j + 10, tj.begin() + 10 * d);
+    dl[d] = d;
+    ap[d] = A + (size_t)d * a_size;
+  }
+  return batched_impl(c, n, tj.data(), dl.data(), bp.data(), ap.data(), lay.data());
 }
 
 int eprl_contract_boundary(eprl_ctx *c, const int dims_i[5], const double *A,

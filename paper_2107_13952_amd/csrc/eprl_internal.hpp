@@ -149,10 +149,12 @@ hipError_t launch_wide_batch(const RingParams *cfgs_dev, const int *items_dev, i
 // Splits the cores of the factorised path, for each i1, into chunks of equal estimated cost
 // (x iterations plus the per-core set-up), about target_wg workgroups in all and at most
 // kRingMaxPartialBytes of partial sums; fills bounds ([i1][nchunk + 1]) and, if asked for, the
-// estimated cost of each chunk ([i1][nchunk], in x iterations) and returns nchunk.
+// estimated cost of each chunk ([i1][nchunk], in x iterations) and returns nchunk.  Only the
+// cores [core_lo, core_hi) are split (core_hi < 0: all); core index
+// ((o24 * nd + o25) * nd + o34) * nd + o35 over the offsets of l24, l25, l34, l35.
 constexpr size_t kRingMaxPartialBytes = size_t(256) << 20;
 int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds,
-                  std::vector<double> *chunk_cost = nullptr);
+                  std::vector<double> *chunk_cost = nullptr, int core_lo = 0, int core_hi = -1);
 int ring_row_blocks(const Plan &p);
 // LDS bytes of the tile class at nd with staging level stg (-1: the most that fits).
 size_t ring_smem_bytes(int cls, int nd, int stg = -1);

@@ -221,24 +221,22 @@ int make_plan(const int two_j[10], int dl, Plan &p, std::string &err) {
 }
 
 int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds,
-                  std::vector<double> *chunk_cost) {
+                  std::vector<double> *chunk_cost, int core_lo, int core_hi) {
   const int nd = p.nd, nd3 = nd * nd * nd, d1 = p.i[0].n;
   const int ncore = nd * nd3;
+  if (core_hi < 0) core_hi = ncore;
+  const int nrange = std::max(1, core_hi - core_lo);
   const int nrb = p.ring_cls >= 0 ? ring_row_blocks(p) : 1;
   int nchunk = std::max(1, target_wg / (d1 * nrb));
   nchunk = (int)std::min<int64_t>(nchunk, std::max<int64_t>(1, (int64_t)(kRingMaxPartialBytes / ((size_t)p.a_size * sizeof(double)))));
-  nchunk = std::min(nchunk, ncore);
+  nchunk = std::min(nchunk, nrange);
   const int *J = p.two_j;
   const int xlo_g = p.X.lo2, xhi_g = p.X.lo2 + 2 * (p.X.n - 1);
   std::vector<double> cost((size_t)d1 * ncore, 0.0);
-  for (int core = 0; core < ncore; ++core) {
-    // Core order of the kernel: (l24, l25, l34, l35) with l35 fastest, or for the wide kernel
-    // (l24, l34, l35, l25) with l25 fastest.
-    const bool wide = p.ring_cls == kWideClass;
-    const int o24 = core / nd3;
-    const int o25 = wide ? core % nd : (core / (nd * nd)) % nd;
-    const int o34 = wide ? (core / (nd * nd)) % nd : (core / nd) % nd;
-    const int o35 = wide ? (core / nd) % nd : core % nd;
+  for (int core = core_lo; core < core_hi; ++core) {
+    // Core order of the kernels: (l24, l25, l34, l35) with l35 fastest.
+    const int o24 = core / nd3, o25 = (core / (nd * nd)) % nd;
+    const int o34 = (core / nd) % nd, o35 = core % nd;
     // Windows of k4 over l45 and of k3 over l23 (pairs with an empty range left out), as the
     // kernel forms them.
     int w4lo = 1 << 30, w4hi = -1, w3lo = 1 << 30, w3hi = -1;
@@ -282,17 +280,17 @@ int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds,
   for (int n1 = 0; n1 < d1; ++n1) {
     const double *cs = cost.data() + (size_t)n1 * ncore;
     double total = 0.0;
-    for (int k = 0; k < ncore; ++k) total += cs[k];
+    for (int k = core_lo; k < core_hi; ++k) total += cs[k];
     int *bd = bounds.data() + (size_t)n1 * (nchunk + 1);
     double run = 0.0;
-    int k = 0;
+    int k = core_lo;
     for (int ch = 1; ch < nchunk; ++ch) {
       const double target = total * ch / nchunk;
-      while (k < ncore && run + 0.5 * cs[k] < target) run += cs[k++];
+      while (k < core_hi && run + 0.5 * cs[k] < target) run += cs[k++];
       bd[ch] = k;
     }
-    bd[0] = 0;
-    bd[nchunk] = ncore;
+    bd[0] = core_lo;
+    bd[nchunk] = core_hi;
     if (chunk_cost)
       for (int ch = 0; ch < nchunk; ++ch)
         for (int q = bd[ch]; q < bd[ch + 1]; ++q) (*chunk_cost)[(size_t)n1 * nchunk + ch] += cs[q];

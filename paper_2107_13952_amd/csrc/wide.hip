@@ -119,9 +119,8 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
   const int c0 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index];
   const int c1 = rp.bounds[(int64_t)n1 * (rp.nchunk + 1) + chunk_index + 1];
   for (int core = c0; core < c1; ++core) {
-    // Cores run with l25 fastest: consecutive cores of a chunk then share the U2, U3, U4 slices
-    // and the M4, M3 blocks (none depends on l25), which stay in the caches.
-    const int o24 = core / nd3, o34 = (core / (nd * nd)) % nd, o35 = (core / nd) % nd, o25 = core % nd;
+    // Core index ((l24 * nd + l25) * nd + l34) * nd + l35 in offsets from the lowest spins.
+    const int o24 = core / nd3, o25 = (core / (nd * nd)) % nd, o34 = (core / nd) % nd, o35 = core % nd;
     const int l24 = J[L24] + 2 * o24, l25 = J[L25] + 2 * o25, l35 = J[L35] + 2 * o35;
     __syncthreads();  // previous readers of rng / bo (and of the LDS tiles) are done
     for (int o = tid; o < nd; o += WT) {

@@ -249,6 +249,95 @@ def test_range_additivity_and_determinism(lib, torch):
     assert normwise(mid, ref) <= TOL
 
 
+def core_index(shell, nd):
+    """Core of a shell (o23, o24, o25, o34, o35, o45): ((o24 nd + o25) nd + o34) nd + o35."""
+    return ((shell[1] * nd + shell[2]) * nd + shell[3]) * nd + shell[4]
+
+
+# A 7^5 tensor in the 8-wide factorised kernel and an 11-dimensional one in the all-matrix-core
+# kernel.
+CORE_CASES = [([6] * 10, 2, 22, 0), ([13, 10, 11, 12, 10, 14, 11, 13, 13, 10], 1, 23, 8)]
+
+
+@pytest.mark.parametrize("two_j,dl,seed,cls", CORE_CASES)
+def test_core_ranges(lib, torch, two_j, dl, seed, cls):
+    """Partial sums over ranges of cores (l24, l25, l34, l35) in the factorised order: the whole
+    range gives the bits of the plain call, two ragged halves add up to the full tensor, a range
+    matches the oracle on its shells, an empty range gives zeros, and invalid ranges are refused."""
+    assert lib.count_work(two_j, dl)["ring_class"] == cls
+    b, bd = boosters_for(torch, two_j, dl, seed)
+    nd = dl + 1
+    ncore = nd ** 4
+    cut = ncore // 3 + 1
+    ref_part = V.vertex_tensor(two_j, dl, b,
+                               shells=[s for s in R.all_shells(dl) if core_index(s, nd) < cut])
+    for algo in ("auto", "ring_valu"):
+        lib.set_algorithm(algo)
+        try:
+            note(f"core ranges [{algo}] {two_j} dl={dl} cut={cut}/{ncore}")
+            full = lib.vertex_tensor(two_j, dl, 1.2, bd)
+            whole = lib.vertex_tensor_cores(two_j, dl, 1.2, bd, 0, ncore)
+            assert torch.equal(full, whole)
+            part = lib.vertex_tensor_cores(two_j, dl, 1.2, bd, 0, cut)
+            err = normwise(part.cpu().numpy(), ref_part)
+            note(f"  first range vs oracle {err:.3e}")
+            assert err <= TOL
+            lib.vertex_tensor_cores(two_j, dl, 1.2, bd, cut, ncore, accumulate=True, out=part)
+            err = normwise(part.cpu().numpy(), full.cpu().numpy())
+            note(f"  halves vs full {err:.3e}")
+            assert err <= 1e-13
+            empty = lib.vertex_tensor_cores(two_j, dl, 1.2, bd, cut, cut)
+            assert not empty.any()
+            for lo, hi in ((0, ncore + 1), (-1, 3), (5, 4)):
+                with pytest.raises(lib.EprlError) as exc:
+                    lib.vertex_tensor_cores(two_j, dl, 1.2, bd, lo, hi)
+                assert exc.value.code == -1
+        finally:
+            lib.set_algorithm("auto")
+    lib.set_algorithm("shell")
+    try:
+        with pytest.raises(lib.EprlError) as exc:
+            lib.vertex_tensor_cores(two_j, dl, 1.2, bd, 0, ncore)
+        assert exc.value.code == -1
+    finally:
+        lib.set_algorithm("auto")
+
+
+def sub_boosters(two_j, dl_max, dl, b):
+    """The packed boosters of dl taken out of a buffer packed for dl_max (same blocks, found by
+    their offsets in the larger layout)."""
+    _, offs = R.booster_layout(two_j, dl_max)
+    n3 = (dl_max + 1) ** 3
+    parts = []
+    for e in range(4):
+        for o1 in range(dl + 1):
+            for o2 in range(dl + 1):
+                for o3 in range(dl + 1):
+                    q = e * n3 + (o1 * (dl_max + 1) + o2) * (dl_max + 1) + o3
+                    parts.append(b[offs[q]:offs[q + 1]])
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("two_j,dl_max,seed", [([2] * 10, 3, 24),
+                                               ([13, 10, 11, 12, 10, 14, 11, 13, 13, 10], 1, 25)])
+def test_shell_scan(lib, torch, two_j, dl_max, seed):
+    """A(dl) for dl = 0..dl_max from one buffer packed for dl_max: each against the oracle at
+    that dl and bitwise against the plain call on its own packed boosters."""
+    b, bd = boosters_for(torch, two_j, dl_max, seed)
+    note(f"shell scan {two_j} dl_max={dl_max}")
+    scan = lib.vertex_tensor_scan(two_j, dl_max, 1.2, bd)
+    assert scan.shape[0] == dl_max + 1
+    for dl in range(dl_max + 1):
+        bs = sub_boosters(two_j, dl_max, dl, b)
+        err = normwise(scan[dl].cpu().numpy(), V.vertex_tensor(two_j, dl, bs))
+        note(f"  dl={dl}: normwise error {err:.3e}")
+        assert err <= TOL
+        plain = lib.vertex_tensor(two_j, dl, 1.2, torch.from_numpy(bs).cuda())
+        assert torch.equal(plain, scan[dl])
+    again = lib.vertex_tensor_scan(two_j, dl_max, 1.2, bd)      # graph replay
+    assert torch.equal(again, scan)
+
+
 def test_cfg2_full_size(lib, torch):
     """j = 3, dl = 8 at full size, in the launch configuration of the benchmark: the
     per-shell path on a contiguous block of shells against the oracle; both paths on the full
