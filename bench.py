@@ -18,8 +18,9 @@ Prints one JSON line:
   cpu_baseline the CPU oracle timed on a bounded sample of the same workload, on every host core
   batched_vs_plain  forward only: the batched call against 16 plain calls (median of replays)
   Extra blocks: the equilateral j = 3, dl = 8 plain vertex (``plain_j3_dl8``), the 64-configuration
-  irregular batch (``irregular_batch``), the j = 3 shell scan dl = 0..8 (``shell_scan_j3``) and
-  the j = 4, dl = 8 differentiation check (``differentiation``).
+  irregular batch (``irregular_batch``), the j = 3 shell scan dl = 0..8 (``shell_scan_j3``), the
+  device booster builder on the j = 3, dl = 8 vertex (``booster_builder_j3_dl8``) and the j = 4,
+  dl = 8 differentiation check (``differentiation``).
 """
 import argparse
 import hashlib
@@ -261,6 +262,25 @@ def shell_scan(lib, torch, dev, reps):
             "single_dl8_terms": lib.count_terms(two_j, dl_max)[1]}
 
 
+def booster_builder(lib, torch, dev, reps):
+    """The boosters of the equilateral j = 3, dl = 8 vertex (eq. (booster), 2916 blocks) by the
+    device quadrature, against the oracle's quadrature stored beside the j = 3 parity tensor."""
+    cfg = workloads.CFG2
+    two_j, dl = cfg["two_j"], cfg["dl"]
+    _, _, offs = lib.layout(two_j, dl)
+    out = torch.empty(int(offs[-1]), dtype=torch.float64, device=dev)
+    _, info = lib.boosters(two_j, dl, 1.2, out=out)
+    ms = event_times(torch, lambda: lib.boosters(two_j, dl, 1.2, out=out), reps)
+    ref = quadrature_boosters(two_j, dl, int(offs[-1]))
+    err = None
+    if ref is not None:
+        err = float(np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max())
+    return {"workload": "boosters of the equilateral j=3 (two_j=6), dl=8 vertex, gamma=1.2, "
+                        f"{int(offs[-1])} values", "time": spread(ms), "subintervals": info["n"],
+            "error_estimate": info["error"], "max_imag": info["imag"],
+            "normwise_vs_oracle_quadrature": err}
+
+
 def differentiation(lib, torch, dev):
     """j=4, dl=8 vertex contracted with five seeded boundary vectors: forward, contraction and
     adjoint times, and the adjoint's booster gradient against central differences along one random
@@ -463,6 +483,8 @@ def main():
         result["irregular_batch"] = irregular_batch(lib, torch, dev, 5)
         progress("shell scan j=3 dl=0..8")
         result["shell_scan_j3"] = shell_scan(lib, torch, dev, 5)
+        progress("booster builder j=3 dl=8")
+        result["booster_builder_j3_dl8"] = booster_builder(lib, torch, dev, 3)
         progress("differentiation j=4 dl=8")
         result["differentiation"] = differentiation(lib, torch, dev)
     if cpu is not None:

@@ -217,6 +217,38 @@ int eprl_contract_boundary(eprl_ctx *ctx, const int dims_i[5], const double *A,
 int eprl_contract_boundary_noalloc(eprl_ctx *ctx, const int dims_i[5], const double *A,
                                    const double *const psi[5], double *F);
 
+/* Complete contraction of two vertex tensors (the two-vertex test of Sec. 3.3 "Tensor
+ * contractions on CPU and GPU"; vertex tensors glued over all five intertwiners, Sec. 3.1
+ * "Tensor contractions"):
+ *   F = sum_{i1..i5} A(i1..i5) B(i1..i5).
+ * A, B: device FP64, prod(dims_i) entries each in the same layout; F: device, one double.
+ * Summed in a fixed order (bitwise repeatable).  EPRL_EINVAL for a non-positive dimension. */
+int eprl_contract_vertices(eprl_ctx *ctx, const int dims_i[5], const double *A, const double *B,
+                           double *F);
+
+/* Partial contraction of a vertex with boundary vectors on its last m intertwiners, leaving a
+ * tensor in the first 5 - m (each vertex of the Delta_3 amplitude of Sec. 4.2 keeps its two
+ * bulk intertwiners; the paper's contract(v, c3, c2, c1) on its column-major A^{i5..i1} pairs
+ * c3 with i5, c2 with i4, c1 with i3, i.e. psi = {c1, c2, c3} here):
+ *   T(i1..i_{5-m}) = sum_{i_{6-m}..i5} A(i1..i5) psi[0](i_{6-m}) ... psi[m-1](i5)
+ * without complex conjugation.  A: device FP64 [i1..i5]; psi: host array of m device complex
+ * vectors (interleaved re, im) of lengths dims_i[5-m..4]; T: device complex, row-major over
+ * (i1..i_{5-m}) (one complex number for m = 5, which is eprl_contract_boundary).  Fixed-order
+ * sums.  EPRL_EINVAL for m outside 1..5 or a null vector. */
+int eprl_contract_trailing(eprl_ctx *ctx, const int dims_i[5], const double *A, int m,
+                           const double *const *psi, double *T);
+
+/* Delta_3 amplitude from its three partially contracted vertices (Sec. 4.2, the Delta_3
+ * listing): with the bulk intertwiners k = (two_klo + 2 n') / 2, n' = 0..n-1, and the spin x of
+ * the internal face,
+ *   F = (-1)^x (2x + 1) sum_{k1, k2, k3} (-1)^(k1 + k2 + k3) TA[k1][k2] TB[k3][k1] TC[k2][k3]
+ * (each matrix is the eprl_contract_trailing output of one vertex, m = 3, row-major over its
+ * first two intertwiners; the triangle runs k1 -> k2 -> k3 -> k1).  TA, TB, TC: device complex
+ * n x n; F: device complex.  EPRL_EINVAL unless 1 <= n <= 1024 and two_klo, two_x are even
+ * (integer spins: the phases are then real). */
+int eprl_contract_delta3(eprl_ctx *ctx, int n, int two_klo, int two_x, const double *TA,
+                         const double *TB, const double *TC, double *F);
+
 /* Adjoint of the boundary contraction composed with the vertex tensor.  With g = grad_F
  * (host complex), writes g * dF/dpsi_a (device, complex, length dims_i[a]) and
  * g * dF/dB (device, complex, same packing and size as the boosters) where the derivatives
@@ -227,6 +259,31 @@ int eprl_contract_boundary_adjoint(eprl_ctx *ctx, const int two_j[10], int dl,
                                    const double *boosters, const double *A,
                                    const double *const psi[5], const double grad_F[2],
                                    double *const grad_psi[5], double *grad_boosters);
+
+/* Booster functions of eq. (booster) for every block of a configuration, in the packed layout
+ * of eprl_layout (edges 2..5, offset triples of their virtual links, rows i, columns k), by the
+ * quadrature of Sec. 3.1 "Booster coefficients":
+ *   B4(j, l; i, k) = sum_m 4jm(j; m; i) 4jm(l; m; k)
+ *                    int_0^inf dr sinh^2 r / (4 pi) prod_a d^{(gamma (j_a+1), j_a)}_{j_a l_a m_a}(r)
+ * (Y-map of eq. (booster); 4jm couples (first second)(third fourth) links of the edge).  The r
+ * integral maps u = e^{-r} to (0, 1] and cuts it into n subintervals growing linearly from u = 0,
+ * each with 30- and 61-point Gauss-Legendre rules; n doubles from 16 (at most 512) until the
+ * largest |61-point - 30-point| entry is at most tol times the largest entry.  The boost matrix
+ * elements d come from the principal-series realisation on SU(2) (an s integral of two SU(2) d
+ * functions, 256 Gauss-Legendre points), in the basis convention under which the boosters are
+ * real; B receives the real parts.
+ *   B     device, booster_offsets[last] doubles, overwritten
+ *   info  host, 3 doubles or NULL: the largest error estimate, the largest |imaginary part| of an
+ *         entry, and the n used.
+ * Synchronises with the context's stream once per n tried (the convergence test).  EPRL_EINVAL
+ * for inadmissible spins or non-positive gamma or tol. */
+int eprl_boosters(eprl_ctx *ctx, const int two_j[10], int dl, double gamma, double tol,
+                  double *B, double info[3]);
+
+/* Diagnostic: n Wigner 3jm symbols (j1 j2 j3; m1 m2 m3) (args: n x 6 two-unit values, host
+ * int32, |value| <= 200, EPRL_ERANGE otherwise) with the device routine of the booster builder
+ * (Racah's single sum, exact prefactor, double-double series); out: n doubles (device). */
+int eprl_threejm_batch(eprl_ctx *ctx, int n, const int *args, double *out);
 
 /* Diagnostic: evaluate n 6j symbols {a b c; d e f} (args: n x 6 two_j values, host int32,
  * each in 0..200, EPRL_ERANGE otherwise) with the same device routine the table builder uses;

@@ -16,6 +16,9 @@ Functions mirror the C entry points:
 * ``vertex_tensor_scan(two_j, dl_max, gamma, boosters)``  A(dl) for dl = 0..dl_max, one batch
 * ``contract_boundary(A, psis)``                          contraction with five vectors
 * ``contract_boundary_adjoint(...)``                      its derivatives
+* ``contract_vertices(A, B)``, ``contract_trailing(A, psis)``, ``contract_delta3(...)``
+                                                          multi-vertex contractions
+* ``boosters(two_j, dl, gamma)``                          eq. (booster) by quadrature on the GPU
 * ``VertexContract``                                      torch.autograd.Function of F(psi, B)
 """
 import ctypes
@@ -59,6 +62,14 @@ _SIGS = {
     "eprl_vertex_tensor_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, ctypes.c_double,
                                                   ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
     "eprl_contract_boundary": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp, ctypes.POINTER(ctypes.c_void_p), _dp]),
+    "eprl_boosters": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     _dp, ctypes.POINTER(ctypes.c_double)]),
+    "eprl_threejm_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _dp]),
+    "eprl_contract_vertices": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp, _dp, _dp]),
+    "eprl_contract_trailing": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp, ctypes.c_int,
+                                              ctypes.POINTER(ctypes.c_void_p), _dp]),
+    "eprl_contract_delta3": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            _dp, _dp, _dp, _dp]),
     "eprl_contract_boundary_noalloc": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp, ctypes.POINTER(ctypes.c_void_p), _dp]),
     "eprl_contract_boundary_adjoint": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int, _dp, _dp,
                                                       ctypes.POINTER(ctypes.c_void_p),
@@ -315,6 +326,59 @@ def contract_boundary(A, psis):
     return torch.view_as_complex(F)
 
 
+def contract_vertices(A, B):
+    """sum_i A(i) B(i) of two float64 vertex tensors of the same shape (0-d device tensor)."""
+    torch = _torch()
+    ap = _check_dev(A, torch.float64, "A")
+    bp = _check_dev(B, torch.float64, "B")
+    dims = list(A.shape)
+    if len(dims) != 5 or list(B.shape) != dims:
+        raise ValueError("A and B must be five-index tensors of the same shape")
+    F = torch.empty((), dtype=torch.float64, device=A.device)
+    ctx = _ctx(A.device)
+    ctx.check(_lib.eprl_contract_vertices(ctx.bind(), _ints(dims, 5), ap, bp, ctypes.c_void_p(F.data_ptr())))
+    return F
+
+
+def contract_trailing(A, psis):
+    """A contracted with len(psis) = m vectors on its last m intertwiners (psis[0] pairs with
+    i_{6-m}, psis[-1] with i5): complex128 tensor over the first 5 - m intertwiners."""
+    torch = _torch()
+    ap = _check_dev(A, torch.float64, "A")
+    dims = list(A.shape)
+    m = len(psis)
+    if len(dims) != 5 or not 1 <= m <= 5:
+        raise ValueError("A must have five indices and between one and five vectors are given")
+    ptrs = []
+    for q, p in enumerate(psis):
+        n = dims[5 - m + q]
+        if p.shape != (n,):
+            raise ValueError(f"vector {q} must have length {n}")
+        ptrs.append(_check_dev(p, torch.complex128, f"psi[{q}]").value)
+    T = torch.empty(dims[:5 - m] + [2], dtype=torch.float64, device=A.device)
+    ctx = _ctx(A.device)
+    ctx.check(_lib.eprl_contract_trailing(ctx.bind(), _ints(dims, 5), ap, m, (ctypes.c_void_p * m)(*ptrs),
+                                          ctypes.c_void_p(T.data_ptr())))
+    return torch.view_as_complex(T)
+
+
+def contract_delta3(TA, TB, TC, two_klo, two_x):
+    """Delta_3 amplitude (-1)^x (2x+1) sum (-1)^(k1+k2+k3) TA[k1,k2] TB[k3,k1] TC[k2,k3] from three
+    complex128 n x n device matrices (0-d complex device tensor)."""
+    torch = _torch()
+    n = TA.shape[0]
+    ptrs = []
+    for name, t in (("TA", TA), ("TB", TB), ("TC", TC)):
+        if tuple(t.shape) != (n, n):
+            raise ValueError(f"{name} must be {n} x {n}")
+        ptrs.append(_check_dev(t, torch.complex128, name))
+    F = torch.empty(2, dtype=torch.float64, device=TA.device)
+    ctx = _ctx(TA.device)
+    ctx.check(_lib.eprl_contract_delta3(ctx.bind(), int(n), int(two_klo), int(two_x), *ptrs,
+                                        ctypes.c_void_p(F.data_ptr())))
+    return torch.view_as_complex(F)
+
+
 def contract_boundary_noalloc(A, psis, F):
     """contract_boundary into a caller-given float64 device tensor F of 2 entries (re, im); the
     library allocates nothing (its partial sums use a fixed device array)."""
@@ -352,6 +416,34 @@ def contract_boundary_adjoint(two_j, dl, boosters, A, psis, grad_F=1.0, want_psi
         ctx.bind(), _ints(two_j, 10), int(dl), bp, ap, _psi_ptrs(psis, dims), gbuf,
         gpsi_ptrs, ctypes.c_void_p(gb.data_ptr()) if want_boosters else None))
     return gpsi, gb
+
+
+def boosters(two_j, dl, gamma, tol=1e-13, device="cuda", out=None):
+    """Packed boosters of eq. (booster) (layout(two_j, dl)) computed on the GPU.  Returns the
+    float64 device tensor and a dict with the largest quadrature error estimate, the largest
+    imaginary part and the number n of subintervals used."""
+    torch = _torch()
+    _, _, offs = _layout(tuple(int(v) for v in two_j), int(dl))
+    if out is None:
+        out = torch.empty(int(offs[-1]), dtype=torch.float64, device=device)
+    bp = _check_dev(out, torch.float64, "out")
+    if out.numel() != int(offs[-1]):
+        raise ValueError(f"output holds {out.numel()} values, layout needs {int(offs[-1])}")
+    info = (ctypes.c_double * 3)()
+    ctx = _ctx(out.device)
+    ctx.check(_lib.eprl_boosters(ctx.bind(), _ints(two_j, 10), int(dl), float(gamma), float(tol), bp, info))
+    return out, {"error": info[0], "imag": info[1], "n": int(info[2])}
+
+
+def threejm_batch(args, device="cuda"):
+    """Evaluate 3jm symbols on the GPU; args is an (n, 6) integer array (two_j1..3, two_m1..3)."""
+    torch = _torch()
+    a = np.ascontiguousarray(np.asarray(args, dtype=np.int32).reshape(-1, 6))
+    out = torch.empty(a.shape[0], dtype=torch.float64, device=device)
+    ctx = _ctx(out.device)
+    ctx.check(_lib.eprl_threejm_batch(ctx.bind(), a.shape[0], a.ctypes.data_as(_i32p),
+                                      ctypes.c_void_p(out.data_ptr())))
+    return out
 
 
 def sixj_batch(args, device="cuda"):

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeprl.so")
-SOURCES = ["sixj.hip", "assemble.hip", "ring.hip", "wide.hip", "contract.hip", "adjoint_ring.hip",
+SOURCES = ["sixj.hip", "assemble.hip", "ring.hip", "wide.hip", "contract.hip", "adjoint_ring.hip", "network.hip", "boosters.hip",
            "eprl_plan.cpp", "api.cpp"]
 
 FLAGS = [

@@ -22,6 +22,8 @@
 // traces.  One workgroup per core accumulates its G vectors over x and writes them out; a second
 // kernel sums, for every booster entry, the G of the cores that share its block, in a fixed
 // order (no atomics: the result is bitwise repeatable).
+#include <algorithm>
+
 #include "eprl_internal.hpp"
 
 namespace eprl {
@@ -50,54 +52,59 @@ constexpr int AT = 256;  // threads per workgroup
 struct PsiPtrs {
   const double *p[5];
 };
-constexpr int KL = 16;   // k values of one block (virtual intertwiner ranges are at most 16)
-constexpr int IW = 16;   // i1 values
-constexpr int KWIN = 32; // k values of a core window (union over l45 or l23)
-
-// LDS layout (complex unless noted); per-spin arrays are [nd][KL].
+// LDS layout (complex unless noted), sized by the configuration: kl = largest k range of a spin,
+// iw = number of i1 values, kw = widest core window of k5, k4, k3 or k2 (union over l45 or l23).
+// Per-spin arrays are [nd][kl].  R3 reuses X2 (dead once R4 is formed) and S2 reuses Z5 (dead
+// after the left half).
 struct AdjGeom {
-  int p1, u5, u4, u2, u3, g5, g4, g3, g2;     // [IW] and [nd][KL] vectors
-  int v2;                                      // [nd][KL k3][IW]
-  int x2, r4, x5, r3;                          // [KWIN][IW] or [IW][KWIN]
-  int z5, q5, s2;                              // [IW][KL], [KL][IW], [IW][KL] scratch
-  int u1s, u5s, u3s;                           // real: [IW][KWIN], [KWIN][IW], [KWIN][KWIN]
+  int kl, iw, kw;
+  int p1, u5, u4, u2, u3, g5, g4, g3, g2;     // [iw] and [nd][kl] vectors
+  int v2;                                      // [nd][kl k3][iw]
+  int x2, r4, x5, r3;                          // [kw][iw] or [iw][kw]
+  int z5, q5, s2;                              // [iw][kl], [kl][iw], [iw][kl] scratch
+  int u1s, u5s, u3s;                           // real: [iw][kw], [kw][iw], [kw][kw]
   int meta;                                    // ints: rng [8][nd], then int64 bo [4][nd]
   size_t bytes;
 };
 
-__host__ __device__ inline AdjGeom adj_geom(int nd) {
+__host__ __device__ inline AdjGeom adj_geom(int nd, int kl, int iw, int kw) {
   AdjGeom g;
+  g.kl = kl;
+  g.iw = iw;
+  g.kw = kw;
   int c = 0;  // in complex units (16 bytes)
-  g.p1 = c; c += IW;
-  g.u5 = c; c += nd * KL;
-  g.u4 = c; c += nd * KL;
-  g.u2 = c; c += nd * KL;
-  g.u3 = c; c += nd * KL;
-  g.g5 = c; c += nd * KL;
-  g.g4 = c; c += nd * KL;
-  g.g3 = c; c += nd * KL;
-  g.g2 = c; c += nd * KL;
-  g.v2 = c; c += nd * KL * IW;
-  g.x2 = c; c += KWIN * IW;
-  g.r4 = c; c += KWIN * IW;
-  g.x5 = c; c += IW * KWIN;
-  g.r3 = c; c += IW * KWIN;
-  g.z5 = c; c += IW * KL;
-  g.q5 = c; c += KL * IW;
-  g.s2 = c; c += IW * KL;
+  g.p1 = c; c += iw;
+  g.u5 = c; c += nd * kl;
+  g.u4 = c; c += nd * kl;
+  g.u2 = c; c += nd * kl;
+  g.u3 = c; c += nd * kl;
+  g.g5 = c; c += nd * kl;
+  g.g4 = c; c += nd * kl;
+  g.g3 = c; c += nd * kl;
+  g.g2 = c; c += nd * kl;
+  g.v2 = c; c += nd * kl * iw;
+  g.x2 = c; c += kw * iw;
+  g.r4 = c; c += kw * iw;
+  g.x5 = c; c += iw * kw;
+  g.r3 = g.x2;
+  g.z5 = c; c += iw * kl;
+  g.q5 = c; c += kl * iw;
+  g.s2 = g.z5;
   int d = 2 * c;  // in doubles
-  g.u1s = d; d += IW * KWIN;
-  g.u5s = d; d += KWIN * IW;
-  g.u3s = d; d += KWIN * KWIN;
+  g.u1s = d; d += iw * kw;
+  g.u5s = d; d += kw * iw;
+  g.u3s = d; d += kw * kw;
   g.meta = d;
   g.bytes = sizeof(double) * (size_t)d + sizeof(int) * 8 * (size_t)nd + sizeof(int64_t) * 4 * (size_t)nd;
   return g;
 }
 
-__global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs psi, double *gbuf) {
+__global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs psi, double *gbuf,
+                                                          int KLr, int IWr, int KWr) {
   extern __shared__ double sm[];
   const int nd = rp.nd, nd3 = nd * nd * nd;
-  const AdjGeom geo = adj_geom(nd);
+  const AdjGeom geo = adj_geom(nd, KLr, IWr, KWr);
+  const int kl = geo.kl, iw = geo.iw, kw = geo.kw;
   cplx *cs = reinterpret_cast<cplx *>(sm);
   cplx *P1 = cs + geo.p1, *u5 = cs + geo.u5, *u4 = cs + geo.u4, *u2 = cs + geo.u2, *u3 = cs + geo.u3;
   cplx *G5 = cs + geo.g5, *G4 = cs + geo.g4, *G3 = cs + geo.g3, *G2 = cs + geo.g2;
@@ -137,15 +144,15 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
     bo[2 * nd + o] = rp.boff[0 * nd3 + t2];
     bo[3 * nd + o] = rp.boff[1 * nd3 + t3];
   }
-  for (int q = tid; q < 4 * nd * KL; q += AT) G5[q] = cplx{0.0, 0.0};  // G5, G4, G3, G2 are adjacent
-  for (int q = tid; q < IW; q += AT)
+  for (int q = tid; q < 4 * nd * kl; q += AT) G5[q] = cplx{0.0, 0.0};  // G5, G4, G3, G2 are adjacent
+  for (int q = tid; q < iw; q += AT)
     P1[q] = q < d1 ? cscale(load_c(psi.p[0], q), __builtin_sqrt((double)(rp.i_lo2[0] + 2 * q + 1)))
                    : cplx{0.0, 0.0};
   __syncthreads();
   // Contracted boosters u_e(k; l) of this core: edge slot s = 0 u5 (l45), 1 u4 (l45), 2 u2 (l23),
   // 3 u3 (l23); psi of edges 5, 4, 2, 3.
-  for (int q = tid; q < 4 * nd * KL; q += AT) {
-    const int s = q / (nd * KL), o = (q / KL) % nd, k = q % KL;
+  for (int q = tid; q < 4 * nd * kl; q += AT) {
+    const int s = q / (nd * kl), o = (q / kl) % nd, k = q % kl;
     const int ri = s == 0 ? 0 : s == 1 ? 2 : s == 2 ? 4 : 6;
     const int lo = rng[ri * nd + o], n = rng[(ri + 1) * nd + o];
     const int e = s == 0 ? 4 : s == 1 ? 3 : s == 2 ? 1 : 2;  // boundary index of the edge
@@ -158,7 +165,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
         u = cfma(u, p, B[off + (int64_t)i * n + k] * w);
       }
     }
-    cs[(s == 0 ? geo.u5 : s == 1 ? geo.u4 : s == 2 ? geo.u2 : geo.u3) + o * KL + k] = u;
+    cs[(s == 0 ? geo.u5 : s == 1 ? geo.u4 : s == 2 ? geo.u2 : geo.u3) + o * kl + k] = u;
   }
   // Core windows of k4 (over l45), k3 (over l23), k5 (over l45) and k2 (over l23).
   int w4lo = 1 << 30, w4hi = -1, w3lo = 1 << 30, w3hi = -1, w5lo = 1 << 30, w2lo = 1 << 30;
@@ -196,18 +203,18 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
     const int xg = (x - rp.X_lo2) / 2;
     __syncthreads();  // previous x's readers are done
     // Table slices of this x: U1(i1, k5), U5(k2, i1), U3(k4, k3) over the core windows.
-    for (int q = tid; q < IW * KWIN; q += AT) {
-      const int i = q / KWIN, p = q % KWIN;
+    for (int q = tid; q < iw * kw; q += AT) {
+      const int i = q / kw, p = q % kw;
       double v1 = 0.0, v5 = 0.0;
       if (i < d1 && p < nw5)
         v1 = rp.U1[(((int64_t)o25 * NX + xg) * d1 + i) * nK5 + ((w5lo - rp.K_lo2[3]) >> 1) + p];
       if (i < d1 && p < nw2)
         v5 = rp.U5[(((int64_t)o25 * NX + xg) * nK2 + ((w2lo - rp.K_lo2[0]) >> 1) + p) * d1 + i];
-      U1s[i * KWIN + p] = v1;
-      U5s[p * IW + i] = v5;
+      U1s[i * kw + p] = v1;
+      U5s[p * iw + i] = v5;
     }
-    for (int q = tid; q < KWIN * KWIN; q += AT) {
-      const int p4 = q / KWIN, p3 = q % KWIN;
+    for (int q = tid; q < kw * kw; q += AT) {
+      const int p4 = q / kw, p3 = q % kw;
       double v = 0.0;
       if (p4 < nw4 && p3 < nw3)
         v = rp.U3[((u3base + xg) * nK4 + ((w4lo - rp.K_lo2[2]) >> 1) + p4) * nK3 +
@@ -216,8 +223,8 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
     }
     __syncthreads();
     // V2_o(k3, i1) = sum_k2 U4(k3, k2; o) u2(k2; o) U5(k2, i1) for every l23 = o.
-    for (int q = tid; q < nd * KL * IW; q += AT) {
-      const int o = q / (KL * IW), k3i = (q / IW) % KL, i = q % IW;
+    for (int q = tid; q < nd * kl * iw; q += AT) {
+      const int o = q / (kl * iw), k3i = (q / iw) % kl, i = q % iw;
       const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
       cplx v{0.0, 0.0};
       if (k3i < n3 && i < d1) {
@@ -226,31 +233,31 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
                             ((lo2 - rp.K_lo2[0]) >> 1);
         const int p2 = (lo2 - w2lo) >> 1;
         for (int k2i = 0; k2i < n2; ++k2i)
-          v = cfma(v, u2[o * KL + k2i], u4r[k2i] * U5s[(p2 + k2i) * IW + i]);
+          v = cfma(v, u2[o * kl + k2i], u4r[k2i] * U5s[(p2 + k2i) * iw + i]);
       }
       V2[q] = v;
     }
     __syncthreads();
     // X2(k3, i1) = sum_o u3(k3; o) V2_o(k3, i1), k3 over the core window.
-    for (int q = tid; q < KWIN * IW; q += AT) {
-      const int p3 = q / IW, i = q % IW;
+    for (int q = tid; q < kw * iw; q += AT) {
+      const int p3 = q / iw, i = q % iw;
       cplx v{0.0, 0.0};
       if (p3 < nw3) {
         const int k3 = w3lo + 2 * p3;
         for (int o = 0; o < nd; ++o) {
           const int lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o], k3i = (k3 - lo3) >> 1;
-          if (n3 > 0 && k3 >= lo3 && k3i < n3) v = cadd(v, cmul(u3[o * KL + k3i], V2[(o * KL + k3i) * IW + i]));
+          if (n3 > 0 && k3 >= lo3 && k3i < n3) v = cadd(v, cmul(u3[o * kl + k3i], V2[(o * kl + k3i) * iw + i]));
         }
       }
       X2[q] = v;
     }
     __syncthreads();
     // R4(k4, i1) = sum_k3 U3(k4, k3) X2(k3, i1); X5 cleared.
-    for (int q = tid; q < KWIN * IW; q += AT) {
-      const int p4 = q / IW, i = q % IW;
+    for (int q = tid; q < kw * iw; q += AT) {
+      const int p4 = q / iw, i = q % iw;
       cplx v{0.0, 0.0};
       if (p4 < nw4)
-        for (int p3 = 0; p3 < nw3; ++p3) v = cfma(v, X2[p3 * IW + i], U3s[p4 * KWIN + p3]);
+        for (int p3 = 0; p3 < nw3; ++p3) v = cfma(v, X2[p3 * iw + i], U3s[p4 * kw + p3]);
       R4[q] = v;
       X5[q] = cplx{0.0, 0.0};
     }
@@ -263,56 +270,56 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
       const double *u2b = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5 + ((lo5 - rp.K_lo2[3]) >> 1)) * nK4 +
                           ((lo4 - rp.K_lo2[2]) >> 1);
       // Z5(i1, k4) = p1(i1) sum_k5 U1(i1, k5) u5(k5) U2(k5, k4)
-      for (int q = tid; q < IW * KL; q += AT) {
-        const int i = q / KL, k4i = q % KL;
+      for (int q = tid; q < iw * kl; q += AT) {
+        const int i = q / kl, k4i = q % kl;
         cplx v{0.0, 0.0};
         if (i < d1 && k4i < n4) {
           for (int k5i = 0; k5i < n5; ++k5i)
-            v = cfma(v, u5[o * KL + k5i], U1s[i * KWIN + p5 + k5i] * u2b[(int64_t)k5i * nK4 + k4i]);
+            v = cfma(v, u5[o * kl + k5i], U1s[i * kw + p5 + k5i] * u2b[(int64_t)k5i * nK4 + k4i]);
           v = cmul(v, P1[i]);
         }
         Z5[q] = v;
       }
       // Q5(k5, i1) = sum_k4 U2(k5, k4) u4(k4) R4(k4, i1)
-      for (int q = tid; q < KL * IW; q += AT) {
-        const int k5i = q / IW, i = q % IW;
+      for (int q = tid; q < kl * iw; q += AT) {
+        const int k5i = q / iw, i = q % iw;
         cplx v{0.0, 0.0};
         if (k5i < n5 && i < d1)
           for (int k4i = 0; k4i < n4; ++k4i)
-            v = cadd(v, cmul(u4[o * KL + k4i], cscale(R4[(p4 + k4i) * IW + i], u2b[(int64_t)k5i * nK4 + k4i])));
+            v = cadd(v, cmul(u4[o * kl + k4i], cscale(R4[(p4 + k4i) * iw + i], u2b[(int64_t)k5i * nK4 + k4i])));
         Q5[q] = v;
       }
       __syncthreads();
       // G4(k4) += sum_i1 Z5(i1, k4) R4(k4, i1);  G5(k5) += sum_i1 p1(i1) U1(i1, k5) Q5(k5, i1);
       // X5(i1, k4) += Z5(i1, k4) u4(k4)
-      for (int q = tid; q < 2 * KL + IW * KL; q += AT) {
-        if (q < KL) {
+      for (int q = tid; q < 2 * kl + iw * kl; q += AT) {
+        if (q < kl) {
           const int k4i = q;
           if (k4i < n4) {
             cplx v{0.0, 0.0};
-            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(Z5[i * KL + k4i], R4[(p4 + k4i) * IW + i]));
-            G4[o * KL + k4i] = cadd(G4[o * KL + k4i], v);
+            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(Z5[i * kl + k4i], R4[(p4 + k4i) * iw + i]));
+            G4[o * kl + k4i] = cadd(G4[o * kl + k4i], v);
           }
-        } else if (q < 2 * KL) {
-          const int k5i = q - KL;
+        } else if (q < 2 * kl) {
+          const int k5i = q - kl;
           if (k5i < n5) {
             cplx v{0.0, 0.0};
-            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(P1[i], cscale(Q5[k5i * IW + i], U1s[i * KWIN + p5 + k5i])));
-            G5[o * KL + k5i] = cadd(G5[o * KL + k5i], v);
+            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(P1[i], cscale(Q5[k5i * iw + i], U1s[i * kw + p5 + k5i])));
+            G5[o * kl + k5i] = cadd(G5[o * kl + k5i], v);
           }
         } else {
-          const int r = q - 2 * KL, i = r / KL, k4i = r % KL;
-          if (i < d1 && k4i < n4) X5[i * KWIN + p4 + k4i] = cadd(X5[i * KWIN + p4 + k4i], cmul(Z5[r], u4[o * KL + k4i]));
+          const int r = q - 2 * kl, i = r / kl, k4i = r % kl;
+          if (i < d1 && k4i < n4) X5[i * kw + p4 + k4i] = cadd(X5[i * kw + p4 + k4i], cmul(Z5[r], u4[o * kl + k4i]));
         }
       }
       __syncthreads();
     }
     // R3(i1, k3) = sum_k4 X5(i1, k4) U3(k4, k3)
-    for (int q = tid; q < IW * KWIN; q += AT) {
-      const int i = q / KWIN, p3 = q % KWIN;
+    for (int q = tid; q < iw * kw; q += AT) {
+      const int i = q / kw, p3 = q % kw;
       cplx v{0.0, 0.0};
       if (p3 < nw3)
-        for (int p4 = 0; p4 < nw4; ++p4) v = cfma(v, X5[i * KWIN + p4], U3s[p4 * KWIN + p3]);
+        for (int p4 = 0; p4 < nw4; ++p4) v = cfma(v, X5[i * kw + p4], U3s[p4 * kw + p3]);
       R3[q] = v;
     }
     __syncthreads();
@@ -324,20 +331,20 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
       const double *u4b = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + ((lo3 - rp.K_lo2[1]) >> 1)) * nK2 +
                           ((lo2 - rp.K_lo2[0]) >> 1);
       // G3(k3) += sum_i1 R3(i1, k3) V2(k3, i1);  S2(i1, k2) = sum_k3 R3(i1, k3) u3(k3) U4(k3, k2)
-      for (int q = tid; q < KL + IW * KL; q += AT) {
-        if (q < KL) {
+      for (int q = tid; q < kl + iw * kl; q += AT) {
+        if (q < kl) {
           const int k3i = q;
           if (k3i < n3) {
             cplx v{0.0, 0.0};
-            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(R3[i * KWIN + p3 + k3i], V2[(o * KL + k3i) * IW + i]));
-            G3[o * KL + k3i] = cadd(G3[o * KL + k3i], v);
+            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(R3[i * kw + p3 + k3i], V2[(o * kl + k3i) * iw + i]));
+            G3[o * kl + k3i] = cadd(G3[o * kl + k3i], v);
           }
         } else {
-          const int r = q - KL, i = r / KL, k2i = r % KL;
+          const int r = q - kl, i = r / kl, k2i = r % kl;
           cplx v{0.0, 0.0};
           if (i < d1 && k2i < n2)
             for (int k3i = 0; k3i < n3; ++k3i)
-              v = cadd(v, cmul(u3[o * KL + k3i], cscale(R3[i * KWIN + p3 + k3i], u4b[(int64_t)k3i * nK2 + k2i])));
+              v = cadd(v, cmul(u3[o * kl + k3i], cscale(R3[i * kw + p3 + k3i], u4b[(int64_t)k3i * nK2 + k2i])));
           S2[r] = v;
         }
       }
@@ -345,17 +352,17 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
       // G2(k2) += sum_i1 S2(i1, k2) U5(k2, i1)
       for (int k2i = tid; k2i < n2; k2i += AT) {
         cplx v{0.0, 0.0};
-        for (int i = 0; i < d1; ++i) v = cfma(v, S2[i * KL + k2i], U5s[(p2 + k2i) * IW + i]);
-        G2[o * KL + k2i] = cadd(G2[o * KL + k2i], v);
+        for (int i = 0; i < d1; ++i) v = cfma(v, S2[i * kl + k2i], U5s[(p2 + k2i) * iw + i]);
+        G2[o * kl + k2i] = cadd(G2[o * kl + k2i], v);
       }
       __syncthreads();
     }
   }
   __syncthreads();
   // gbuf[core][slot][o][k], slots in booster-edge order: 0 G2, 1 G3, 2 G4, 3 G5.
-  double *out = gbuf + (int64_t)core * 4 * nd * KL * 2;
-  for (int q = tid; q < 4 * nd * KL; q += AT) {
-    const int s = q / (nd * KL), r = q % (nd * KL);
+  double *out = gbuf + (int64_t)core * 4 * nd * kl * 2;
+  for (int q = tid; q < 4 * nd * kl; q += AT) {
+    const int s = q / (nd * kl), r = q % (nd * kl);
     const cplx v = (s == 0 ? G2 : s == 1 ? G3 : s == 2 ? G4 : G5)[r];
     out[2 * q] = v.re;
     out[2 * q + 1] = v.im;
@@ -364,8 +371,8 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
 
 // One thread per booster entry (edge e, triple t, row i, column k): the sum over the nd^2 cores
 // that contain the block, in a fixed order, times g (2k+1) p_e(i).
-__global__ void adjoint_ring_reduce_kernel(RingParams rp, PsiPtrs psi, const double *gbuf, double gre,
-                                           double gim, double *grad_b) {
+__global__ void adjoint_ring_reduce_kernel(RingParams rp, PsiPtrs psi, const double *gbuf, int kl,
+                                           double gre, double gim, double *grad_b) {
   const int nd = rp.nd, nd3 = nd * nd * nd;
   const int64_t total = rp.boff[4 * nd3];
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -395,7 +402,7 @@ __global__ void adjoint_ring_reduce_kernel(RingParams rp, PsiPtrs psi, const dou
     else if (e == 2) { o24 = b; o34 = c; o25 = p; o35 = q; }
     else { o25 = a; o35 = b; o24 = p; o34 = q; }
     const int core = ((o24 * nd + o25) * nd + o34) * nd + o35;
-    const double *g = gbuf + (((int64_t)core * 4 + e) * nd + o) * KL * 2 + 2 * k;
+    const double *g = gbuf + (((int64_t)core * 4 + e) * nd + o) * kl * 2 + 2 * k;
     sre += g[0];
     sim += g[1];
   }
@@ -407,27 +414,61 @@ __global__ void adjoint_ring_reduce_kernel(RingParams rp, PsiPtrs psi, const dou
 
 }  // namespace
 
-size_t adjoint_ring_smem(int nd) { return adj_geom(nd).bytes; }
-size_t adjoint_ring_gbuf_bytes(int nd) {
-  return sizeof(double) * 2 * (size_t)nd * nd * nd * nd * 4 * nd * KL;
+void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw) {
+  const int nd = p.nd, nd3 = nd * nd * nd;
+  kl = std::max(1, p.kmax);
+  iw = std::max(1, p.i[0].n);
+  kw = 1;
+  // Widest window of k5 and k4 over l45, and of k3 and k2 over l23, of any core (spins whose pair
+  // of ranges has an empty member left out, as in the kernel).
+  for (int core = 0; core < nd * nd3; ++core) {
+    const int o24 = core / nd3, o25 = (core / (nd * nd)) % nd, o34 = (core / nd) % nd, o35 = core % nd;
+    int lo[4] = {1 << 30, 1 << 30, 1 << 30, 1 << 30}, hi[4] = {-1, -1, -1, -1};
+    for (int o = 0; o < nd; ++o) {
+      const int t5 = (o25 * nd + o35) * nd + o, t4 = (o * nd + o24) * nd + o34;
+      const int t2 = (o * nd + o24) * nd + o25, t3 = (o34 * nd + o35) * nd + o;
+      const int n5 = p.kr[(3 * nd3 + t5) * 2 + 1], n4 = p.kr[(2 * nd3 + t4) * 2 + 1];
+      const int n2 = p.kr[(0 * nd3 + t2) * 2 + 1], n3 = p.kr[(1 * nd3 + t3) * 2 + 1];
+      const int l5 = p.kr[(3 * nd3 + t5) * 2], l4 = p.kr[(2 * nd3 + t4) * 2];
+      const int l2 = p.kr[(0 * nd3 + t2) * 2], l3 = p.kr[(1 * nd3 + t3) * 2];
+      if (n5 > 0 && n4 > 0) {
+        lo[0] = std::min(lo[0], l5); hi[0] = std::max(hi[0], l5 + 2 * (n5 - 1));
+        lo[1] = std::min(lo[1], l4); hi[1] = std::max(hi[1], l4 + 2 * (n4 - 1));
+      }
+      if (n2 > 0 && n3 > 0) {
+        lo[2] = std::min(lo[2], l3); hi[2] = std::max(hi[2], l3 + 2 * (n3 - 1));
+        lo[3] = std::min(lo[3], l2); hi[3] = std::max(hi[3], l2 + 2 * (n2 - 1));
+      }
+    }
+    for (int q = 0; q < 4; ++q)
+      if (hi[q] >= 0) kw = std::max(kw, (hi[q] - lo[q]) / 2 + 1);
+  }
+}
+
+size_t adjoint_ring_smem(int nd, int kl, int iw, int kw) { return adj_geom(nd, kl, iw, kw).bytes; }
+size_t adjoint_ring_gbuf_bytes(int nd, int kl) {
+  return sizeof(double) * 2 * (size_t)nd * nd * nd * nd * 4 * nd * kl;
 }
 
 hipError_t adjoint_ring_init_attributes() {
   return hipFuncSetAttribute((const void *)adjoint_ring_kernel,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)adj_geom(kAdjRingMaxNd).bytes);
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kAdjRingMaxLds);
 }
 
-hipError_t launch_adjoint_ring(const RingParams &rp, const double *const psi[5], double *gbuf,
-                               int64_t total, double gre, double gim, double *grad_b, hipStream_t s) {
+hipError_t launch_adjoint_ring(const RingParams &rp, int kl, int iw, int kw, const double *const psi[5],
+                               double *gbuf, int64_t total, double gre, double gim, double *grad_b,
+                               hipStream_t s) {
   PsiPtrs pp;
   for (int a = 0; a < 5; ++a) pp.p[a] = psi[a];
   const int nd = rp.nd;
-  if (nd > kAdjRingMaxNd) return hipErrorInvalidValue;
-  adjoint_ring_kernel<<<nd * nd * nd * nd, AT, adj_geom(nd).bytes, s>>>(rp, pp, gbuf);
+  const size_t bytes = adj_geom(nd, kl, iw, kw).bytes;
+  if (nd > kAdjRingMaxNd || bytes > kAdjRingMaxLds) return hipErrorInvalidValue;
+  adjoint_ring_kernel<<<nd * nd * nd * nd, AT, bytes, s>>>(rp, pp, gbuf, kl, iw, kw);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (total <= 0) return hipSuccess;
-  adjoint_ring_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(rp, pp, gbuf, gre, gim, grad_b);
+  adjoint_ring_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(rp, pp, gbuf, kl, gre, gim,
+                                                                            grad_b);
   return hipGetLastError();
 }
 

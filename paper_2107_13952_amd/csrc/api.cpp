@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <new>
 #include <sstream>
 
@@ -28,13 +30,26 @@ struct BatchSeq {
   std::vector<BatchEntry> ent;
   std::vector<const double *> B;
   std::vector<double *> A;
-  int nring = 0, max_nd = 1, ncu = 256;
-  int cls_begin[kRingClasses + 1] = {0};
+  int nring = 0, ncu = 256;
+  // One persistent launch per group of items: a tile class and, for the 8-wide classes, one nd
+  // (their LDS, and so their occupancy, is sized for the group's nd); items [begin, end) of the
+  // work list, estimated cost (sum of item costs), work-queue counter `group index`.
+  struct Group {
+    int cls, nd, begin, end;
+    double cost;
+    int xoff;  // wide class: index (in ints, from items_off) of its nine per-XCD list offsets
+  };
+  std::vector<Group> groups;
   size_t params_off = 0, items_off = 0, counters_off = 0;
 };
 
+// Streams beside the capture stream on which the batch's persistent launches run concurrently
+// inside the captured graph (all at the default priority).
+constexpr int kBatchSide = 3;
+
 struct eprl_ctx {
   int device = 0;
+  int ncu = 256;  // compute units of the device
   hipStream_t stream = nullptr;
   std::string err;
   // grow-only device workspace
@@ -90,6 +105,8 @@ struct eprl_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;  // private stream the graph is captured on (default priority)
+    hipStream_t side[kBatchSide] = {};
+    hipEvent_t fork = nullptr, join[kBatchSide] = {};
     BatchSeq seq;
   } batch;
 };
@@ -427,7 +444,8 @@ int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int acc
   const int nchunk = c->sched_nchunk;
   const size_t pbytes = align_up((size_t)nchunk * probe.a_size * sizeof(double), 256);
   Prepared prep;
-  int rc = prepare(c, two_j, dl, pbytes, prep, true, &bounds, &probe);
+  // Partial sums, then the eight work-queue counters of the persistent wide kernel.
+  int rc = prepare(c, two_j, dl, pbytes + 256, prep, true, &bounds, &probe);
   if (rc) return rc;
   const Plan &p = prep.plan;
   RingParams rp = ring_params(prep, B);
@@ -439,7 +457,7 @@ int ring_impl(eprl_ctx *c, const int two_j[10], int dl, const double *B, int acc
   {
     TimedLaunch tl(c, 4);
     if (p.ring_cls == kWideClass)
-      HIP_TRY(c, launch_wide(rp, c->stream));
+      HIP_TRY(c, launch_wide(rp, reinterpret_cast<int *>(prep.tail + pbytes), c->ncu, c->stream));
     else
       HIP_TRY(c, launch_ring(rp, p.ring_cls, c->tune_stg[p.ring_cls], c->stream));
   }
@@ -540,6 +558,70 @@ int vertex_cores_impl(eprl_ctx *c, const int two_j[10], int dl, double gamma, co
   return ring_impl(c, two_j, dl, B, accumulate, A, probe, (int)cb, (int)ce);
 }
 
+// ---- booster builder (host side) -----------------------------------------------------------
+
+// Gauss-Legendre nodes (ascending) and weights of n points on [-1, 1], by Newton's method on
+// the Legendre recurrence in long double.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    long double z = std::cos(pi * (i + 0.75L) / (n + 0.5L)), dp = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      long double p1 = 1.0L, p2 = 0.0L;
+      for (int k = 1; k <= n; ++k) {
+        const long double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0L * k - 1.0L) * z * p2 - (k - 1.0L) * p3) / k;
+      }
+      dp = n * (z * p1 - p2) / (z * z - 1.0L);
+      const long double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs((double)dz) < 1e-19) break;
+    }
+    x[i] = (double)-z;
+    x[n - 1 - i] = (double)z;
+    w[i] = w[n - 1 - i] = (double)(2.0L / ((1.0L - z * z) * dp * dp));
+  }
+}
+
+// Jacobi-form constants of d^J_{m' m} (two-unit arguments).
+void jacobi_constants(int J2, int mp2, int m2, double &norm, int &mu, int &nu, int &s) {
+  mu = std::abs(m2 - mp2) / 2;
+  nu = std::abs(m2 + mp2) / 2;
+  s = (J2 - std::max(std::abs(m2), std::abs(mp2))) / 2;
+  long double f = 1.0L;
+  for (int q = 1; q <= nu; ++q) f *= (long double)(s + mu + q) / (long double)(s + q);
+  const double xi = (m2 >= mp2 || ((mp2 - m2) / 2) % 2 == 0) ? 1.0 : -1.0;
+  norm = xi * (double)std::sqrt(f);
+}
+
+// r nodes of the booster quadrature with n subintervals of u = e^{-r} in (0, 1], |I_k| =
+// k * 2 / (n (n + 1)): the 30-point rule's nodes, then the 61-point rule's; weights include
+// du / u and sinh^2 r / (4 pi).
+void booster_r_nodes(int n, const std::vector<double> (&gx)[2], const std::vector<double> (&gw)[2],
+                     std::vector<double> &r, std::vector<double> &rw) {
+  r.clear();
+  rw.clear();
+  const double dx = 2.0 / ((double)n * (n + 1));
+  const double four_pi = 4.0 * 3.14159265358979323846;
+  for (int rule = 0; rule < 2; ++rule) {
+    double lo = 0.0;
+    for (int k = 1; k <= n; ++k) {
+      const double hi = k < n ? lo + k * dx : 1.0;
+      for (size_t p = 0; p < gx[rule].size(); ++p) {
+        const double u = lo + (hi - lo) * (gx[rule][p] + 1.0) / 2.0;
+        const double rr = -std::log(u);
+        const double sh = std::sinh(rr);
+        r.push_back(rr);
+        rw.push_back(gw[rule][p] * (hi - lo) / 2.0 / u * sh * sh / four_pi);
+      }
+      lo = hi;
+    }
+  }
+}
+
 // ---- batched path ------------------------------------------------------------------------
 //
 // All configurations of a batch share one dedicated workspace laid out once per batch shape:
@@ -604,10 +686,35 @@ hipError_t enqueue_batch(eprl_ctx *c) {
                : launch_sixj_tables(tp, b.plan.toff[5], c->stream);
   }
   int *counters = reinterpret_cast<int *>(ws + seq.counters_off);
-  if (e == hipSuccess && seq.nring > 0) e = launch_reset_counters(counters, kRingClasses, c->stream);
-  for (int cls = 0; cls < kRingClasses && e == hipSuccess; ++cls) {
-    const int nit = seq.cls_begin[cls + 1] - seq.cls_begin[cls];
-    if (nit == 0) continue;
+  const int ngroup = (int)seq.groups.size();
+  if (e == hipSuccess && ngroup > 0) e = launch_reset_counters(counters, 8 * ngroup, c->stream);
+  // Inside a capture the groups run on up to 1 + kBatchSide streams (graph branches), the
+  // costliest group first, each on the stream with the least work so far; outside a capture
+  // (timed launches) they run one after the other on the context's stream.
+  hipStream_t main = c->stream;
+  const int nstream = c->capturing ? std::min(ngroup, 1 + kBatchSide) : 1;
+  std::vector<hipStream_t> streams(std::max(nstream, 1), main);
+  if (e == hipSuccess && nstream > 1) {
+    e = hipEventRecord(c->batch.fork, main);
+    for (int q = 1; q < nstream && e == hipSuccess; ++q) {
+      streams[q] = c->batch.side[q - 1];
+      e = hipStreamWaitEvent(streams[q], c->batch.fork, 0);
+    }
+  }
+  std::vector<double> load(streams.size(), 0.0);
+  std::vector<int> order(ngroup);
+  for (int g = 0; g < ngroup; ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return seq.groups[a].cost > seq.groups[b].cost; });
+  for (int oi = 0; oi < ngroup && e == hipSuccess; ++oi) {
+    const int g = order[oi];
+    const BatchSeq::Group &gr = seq.groups[g];
+    const int cls = gr.cls, nit = gr.end - gr.begin;
+    const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[si] += gr.cost;
+    c->stream = streams[si];
+    const int *items = reinterpret_cast<const int *>(ws + seq.items_off) + 4 * gr.begin;
+    const RingParams *params = reinterpret_cast<const RingParams *>(ws + seq.params_off);
     if (cls == kWideClass) {
       // One 8-wavefront workgroup per CU, LDS sized for the largest configuration of the class;
       // booster blocks staged when every configuration's fit.
@@ -622,19 +729,23 @@ hipError_t enqueue_batch(eprl_ctx *c) {
           stg = stg && wide_fits(b.plan.nd, dims, b.plan.ring_kw, b.plan.ring_nrb, true);
         }
       TimedLaunch tl(c, 6);
-      e = launch_wide_batch(reinterpret_cast<const RingParams *>(ws + seq.params_off),
-                            reinterpret_cast<const int *>(ws + seq.items_off) + 4 * seq.cls_begin[cls],
-                            nit, stg ? shm_stg : shm, stg, std::min(nit, seq.ncu), counters + cls, c->stream);
-      continue;
+      const int *xoff = reinterpret_cast<const int *>(ws + seq.items_off) + gr.xoff;
+      e = launch_wide_batch(params, items, xoff, nit, stg ? shm_stg : shm, stg,
+                            std::min(nit, seq.ncu), counters + 8 * g, c->stream);
+    } else {
+      // Enough workgroups to fill the chip at the occupancy the group's LDS allows.
+      const size_t shm = ring_smem_bytes(cls, gr.nd, c->tune_stg[cls]);
+      const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(shm, 1))));
+      const int grid = (int)std::min<int>(nit, seq.ncu * per_cu);
+      TimedLaunch tl(c, 6);
+      e = launch_ring_batch(params, items, nit, cls, gr.nd, c->tune_stg[cls], grid, counters + 8 * g,
+                            c->stream);
     }
-    // Enough workgroups to fill the chip at the occupancy the tile class allows.
-    const size_t shm = ring_smem_bytes(cls, seq.max_nd, c->tune_stg[cls]);
-    const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(shm, 1))));
-    const int grid = (int)std::min<int>(nit, seq.ncu * per_cu);
-    TimedLaunch tl(c, 6);
-    e = launch_ring_batch(reinterpret_cast<const RingParams *>(ws + seq.params_off),
-                          reinterpret_cast<const int *>(ws + seq.items_off) + 4 * seq.cls_begin[cls],
-                          nit, cls, seq.max_nd, c->tune_stg[cls], grid, counters + cls, c->stream);
+  }
+  c->stream = main;
+  for (int q = 1; q < nstream && e == hipSuccess; ++q) {
+    e = hipEventRecord(c->batch.join[q - 1], streams[q]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(main, c->batch.join[q - 1], 0);
   }
   for (int q = 0; q < n && e == hipSuccess; ++q) {
     const BatchEntry &b = seq.ent[q];
@@ -701,7 +812,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   // New batch shape: plan every configuration and lay out the workspace.
   std::vector<BatchEntry> ent(n);
   size_t off = 0;
-  int fact_max = 0, max_nd = 1;
+  int fact_max = 0;
   for (int q = 0; q < n; ++q) {
     BatchEntry &b = ent[q];
     std::string err;
@@ -733,7 +844,6 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     batch_chunks(p, b.ring, p.ring_cls >= 0 ? c->tune_wg[p.ring_cls] : 0, b.nchunk, b.chunk,
                  b.bounds, b.ccost);
     fact_max = std::max(fact_max, p.fact_max);
-    if (b.ring) max_nd = std::max(max_nd, p.nd);
     b.tables = off;
     off += align_up((size_t)p.toff[5] * sizeof(double), 256);
     b.boff = off;
@@ -745,13 +855,14 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     b.partial = off;
     off += align_up((size_t)b.nchunk * p.a_size * sizeof(double), 256);
   }
-  // Work lists of the persistent kernels, one per tile class: (configuration, chunk, i1, row
-  // block), longest first.
+  // Work lists of the persistent kernels, one per group: (configuration, chunk, i1, row block),
+  // longest first.
   struct Item {
     double cost;
     int cfg, chunk, n1, rb;
   };
-  std::vector<Item> cls_items[kRingClasses];
+  // Groups: (tile class, nd) for the 8-wide classes, the whole wide class as one.
+  std::map<std::pair<int, int>, std::vector<Item>> grouped;
   std::vector<int> ring_index(n, -1);
   int nring = 0;
   for (int q = 0; q < n; ++q) {
@@ -762,26 +873,66 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     const Plan &p = ent[q].plan;
     const double slice = (double)p.i[1].n * p.i[2].n * p.i[3].n * p.i[4].n;
     const int cls = p.ring_cls, nrb = ring_row_blocks(p), nch = ent[q].nchunk;
+    std::vector<Item> &dst = grouped[{cls, cls == kWideClass ? 0 : p.nd}];
     for (int ch = 0; ch < nch; ++ch)
       for (int n1 = 0; n1 < p.i[0].n; ++n1) {
         const double cost = ent[q].ccost[(size_t)n1 * nch + ch] * slice;
-        for (int rb = 0; rb < nrb; ++rb) cls_items[cls].push_back({cost, ring_index[q], ch, n1, rb});
+        for (int rb = 0; rb < nrb; ++rb) dst.push_back({cost, ring_index[q], ch, n1, rb});
       }
   }
   std::vector<Item> items;
-  int cls_begin[kRingClasses + 1] = {0};
-  for (int cls = 0; cls < kRingClasses; ++cls) {
-    std::stable_sort(cls_items[cls].begin(), cls_items[cls].end(),
-                     [](const Item &a, const Item &b) { return a.cost > b.cost; });
-    items.insert(items.end(), cls_items[cls].begin(), cls_items[cls].end());
-    cls_begin[cls + 1] = (int)items.size();
+  std::vector<BatchSeq::Group> groups;
+  std::vector<int> xoffs;  // per wide group: nine per-XCD list offsets
+  for (auto &kv : grouped) {
+    std::vector<Item> &v = kv.second;
+    BatchSeq::Group g{kv.first.first, kv.first.second, (int)items.size(), 0, 0.0, -1};
+    for (const Item &it : v) g.cost += it.cost;
+    if (g.cls != kWideClass) {
+      std::stable_sort(v.begin(), v.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+      items.insert(items.end(), v.begin(), v.end());
+    } else {
+      // Chunks (configuration, chunk, row block) with all their i1 items, longest first, each to
+      // the XCD list with the least work so far; in a list the chunks keep that order and the
+      // items of a chunk stay together (longest first).
+      std::map<std::tuple<int, int, int>, std::vector<Item>> chunks;
+      for (const Item &it : v) chunks[std::make_tuple(it.cfg, it.chunk, it.rb)].push_back(it);
+      std::vector<std::pair<double, std::vector<Item> *>> order;
+      for (auto &ck : chunks) {
+        double cost = 0.0;
+        for (const Item &it : ck.second) cost += it.cost;
+        std::stable_sort(ck.second.begin(), ck.second.end(),
+                         [](const Item &a, const Item &b) { return a.cost > b.cost; });
+        order.push_back({cost, &ck.second});
+      }
+      std::stable_sort(order.begin(), order.end(),
+                       [](const std::pair<double, std::vector<Item> *> &a,
+                          const std::pair<double, std::vector<Item> *> &b) { return a.first > b.first; });
+      std::vector<Item> lists[8];
+      double load[8] = {0.0};
+      for (auto &o : order) {
+        const int x = (int)(std::min_element(load, load + 8) - load);
+        load[x] += o.first;
+        lists[x].insert(lists[x].end(), o.second->begin(), o.second->end());
+      }
+      g.xoff = (int)xoffs.size();
+      for (int x = 0; x < 8; ++x) {
+        xoffs.push_back((int)(items.size() - g.begin));
+        items.insert(items.end(), lists[x].begin(), lists[x].end());
+      }
+      xoffs.push_back((int)(items.size() - g.begin));
+    }
+    g.end = (int)items.size();
+    groups.push_back(g);
   }
+  // The per-XCD offsets follow the items in the same device array.
+  for (BatchSeq::Group &g : groups)
+    if (g.xoff >= 0) g.xoff += 4 * (int)items.size();
   const size_t params_off = off;
   off += align_up((size_t)std::max(nring, 1) * sizeof(RingParams), 256);
   const size_t items_off = off;
-  off += align_up(std::max<size_t>(items.size(), 1) * 4 * sizeof(int), 256);
-  const size_t counters_off = off;  // one work-queue counter per tile class
-  off += 256;
+  off += align_up((std::max<size_t>(items.size(), 1) * 4 + xoffs.size()) * sizeof(int), 256);
+  const size_t counters_off = off;  // eight work-queue counters per group
+  off += align_up(std::max<size_t>(groups.size(), 1) * 8 * sizeof(int), 256);
   int rc = ensure_fexp(c, fact_max);
   if (rc) return rc;
   // Drop the previous graph and workspace.
@@ -857,13 +1008,14 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
       so += ent[q].partial - ent[q].boff;
     }
     std::memcpy(st + so, params.data(), params.size() * sizeof(RingParams));
-    std::vector<int> flat(std::max<size_t>(items.size(), 1) * 4, 0);
+    std::vector<int> flat(std::max<size_t>(items.size(), 1) * 4 + xoffs.size(), 0);
     for (size_t k = 0; k < items.size(); ++k) {
       flat[4 * k] = items[k].cfg;
       flat[4 * k + 1] = items[k].chunk;
       flat[4 * k + 2] = items[k].n1;
       flat[4 * k + 3] = items[k].rb;
     }
+    std::copy(xoffs.begin(), xoffs.end(), flat.begin() + 4 * items.size());
     std::memcpy(st + so + (items_off - params_off), flat.data(), flat.size() * sizeof(int));
     so = 0;
     for (auto &b : blocks) {
@@ -879,8 +1031,7 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   seq.B.assign(boosters, boosters + n);
   seq.A.assign(A, A + n);
   seq.nring = nring;
-  seq.max_nd = max_nd;
-  std::copy(cls_begin, cls_begin + kRingClasses + 1, seq.cls_begin);
+  seq.groups = std::move(groups);
   seq.params_off = params_off;
   seq.items_off = items_off;
   seq.counters_off = counters_off;
@@ -889,6 +1040,11 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
   // Capture the device work on a private stream (the caller's stream may be the null stream,
   // which cannot be captured); the graph is then launched on the caller's stream.
   if (!c->batch.cap) HIP_TRY(c, hipStreamCreateWithFlags(&c->batch.cap, hipStreamNonBlocking));
+  if (!c->batch.fork) HIP_TRY(c, hipEventCreateWithFlags(&c->batch.fork, hipEventDisableTiming));
+  for (int q = 0; q < kBatchSide; ++q) {
+    if (!c->batch.side[q]) HIP_TRY(c, hipStreamCreateWithFlags(&c->batch.side[q], hipStreamNonBlocking));
+    if (!c->batch.join[q]) HIP_TRY(c, hipEventCreateWithFlags(&c->batch.join[q], hipEventDisableTiming));
+  }
   hipStream_t user = c->stream;
   c->stream = c->batch.cap;
   hipError_t eb = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
@@ -931,7 +1087,8 @@ int eprl_create(eprl_ctx **out, int device, void *hip_stream) {
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   bool ok = hipSetDevice(device) == hipSuccess && ring_init_attributes() == hipSuccess &&
-            contract_scratch_address(&c->scratch) == hipSuccess;
+            contract_scratch_address(&c->scratch) == hipSuccess &&
+            hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess;
   for (int k = 0; ok && k < eprl_ctx::kStages; ++k)
     ok = hipEventCreateWithFlags(&c->stage_done[k], hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&c->handoff, hipEventDisableTiming) == hipSuccess;
@@ -964,6 +1121,11 @@ void eprl_destroy(eprl_ctx *c) {
   if (c->batch.graph) (void)hipGraphDestroy(c->batch.graph);
   if (c->batch.ws) (void)hipFree(c->batch.ws);
   if (c->batch.cap) (void)hipStreamDestroy(c->batch.cap);
+  for (int q = 0; q < kBatchSide; ++q) {
+    if (c->batch.side[q]) (void)hipStreamDestroy(c->batch.side[q]);
+    if (c->batch.join[q]) (void)hipEventDestroy(c->batch.join[q]);
+  }
+  if (c->batch.fork) (void)hipEventDestroy(c->batch.fork);
   clear_timing(c);
   delete c;
 }
@@ -1196,6 +1358,70 @@ int eprl_contract_boundary(eprl_ctx *c, const int dims_i[5], const double *A,
   return EPRL_OK;
 }
 
+int eprl_contract_vertices(eprl_ctx *c, const int dims_i[5], const double *A, const double *B,
+                           double *F) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!dims_i || !A || !B || !F) return fail(c, EPRL_EINVAL, "null argument");
+  int64_t total = 1;
+  for (int e = 0; e < 5; ++e) {
+    if (dims_i[e] <= 0) return fail(c, EPRL_EINVAL, "invalid dimension");
+    total *= dims_i[e];
+  }
+  const int nblocks = (int)std::min<int64_t>(256, (total + 2047) / 2048);
+  int rc = ensure_workspace(c, (size_t)nblocks * sizeof(double));
+  if (rc) return rc;
+  HIP_TRY(c, launch_contract_vertices(A, B, total, nblocks, reinterpret_cast<double *>(c->ws), F,
+                                      c->stream));
+  return EPRL_OK;
+}
+
+int eprl_contract_trailing(eprl_ctx *c, const int dims_i[5], const double *A, int m,
+                           const double *const *psi, double *T) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!dims_i || !A || !psi || !T) return fail(c, EPRL_EINVAL, "null argument");
+  if (m < 1 || m > 5) return fail(c, EPRL_EINVAL, "between one and five vectors");
+  for (int e = 0; e < 5; ++e)
+    if (dims_i[e] <= 0) return fail(c, EPRL_EINVAL, "invalid dimension");
+  for (int q = 0; q < m; ++q)
+    if (!psi[q]) return fail(c, EPRL_EINVAL, "null vector");
+  if (m == 5) {  // all five: the boundary contraction
+    const double *p5[5] = {psi[0], psi[1], psi[2], psi[3], psi[4]};
+    return eprl_contract_boundary(c, dims_i, A, p5, T);
+  }
+  TrailParams tp;
+  std::memset(&tp, 0, sizeof(tp));
+  tp.A = A;
+  tp.m = m;
+  int64_t nlead = 1;
+  tp.S = 1;
+  for (int e = 0; e < 5 - m; ++e) nlead *= dims_i[e];
+  for (int q = 0; q < m; ++q) {
+    tp.n[q] = dims_i[5 - m + q];
+    tp.psi[q] = psi[q];
+    tp.S *= tp.n[q];
+  }
+  tp.nsplit = trailing_splits(nlead, tp.S);
+  tp.T = T;
+  if (tp.nsplit > 1) {
+    int rc = ensure_workspace(c, (size_t)nlead * tp.nsplit * 2 * sizeof(double));
+    if (rc) return rc;
+    tp.partial = reinterpret_cast<double *>(c->ws);
+  }
+  HIP_TRY(c, launch_contract_trailing(tp, nlead, c->stream));
+  return EPRL_OK;
+}
+
+int eprl_contract_delta3(eprl_ctx *c, int n, int two_klo, int two_x, const double *TA,
+                         const double *TB, const double *TC, double *F) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!TA || !TB || !TC || !F) return fail(c, EPRL_EINVAL, "null argument");
+  if (n < 1 || n > 1024) return fail(c, EPRL_EINVAL, "bulk intertwiner range must hold 1..1024 values");
+  if (two_klo < 0 || two_x < 0 || (two_klo & 1) || (two_x & 1))
+    return fail(c, EPRL_EINVAL, "bulk intertwiners and the internal spin must be integer spins");
+  HIP_TRY(c, launch_delta3(n, two_klo, two_x, TA, TB, TC, F, c->stream));
+  return EPRL_OK;
+}
+
 int eprl_contract_boundary_noalloc(eprl_ctx *c, const int dims_i[5], const double *A,
                                    const double *const psi[5], double *F) {
   if (check_ctx(c)) return EPRL_EINVAL;
@@ -1247,16 +1473,19 @@ int eprl_contract_boundary_adjoint(eprl_ctx *c, const int two_j[10], int dl, con
   if (!grad_boosters) return EPRL_OK;
   if (!B) return fail(c, EPRL_EINVAL, "null booster pointer");
   if (probe.kmax > 16) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
-  if (c->algo != EPRL_ALGO_SHELL && probe.ring_KW != 0 && probe.nd <= kAdjRingMaxNd) {
+  int akl = 0, aiw = 0, akw = 0;
+  if (c->algo != EPRL_ALGO_SHELL && probe.ring_KW != 0 && probe.nd <= kAdjRingMaxNd)
+    adjoint_ring_dims(probe, akl, aiw, akw);
+  if (akl > 0 && adjoint_ring_smem(probe.nd, akl, aiw, akw) <= kAdjRingMaxLds) {
     // Factorised order: per-core G vectors, then a fixed-order sum per booster entry.
     Prepared prep;
-    rc = prepare(c, two_j, dl, align_up(adjoint_ring_gbuf_bytes(probe.nd), 256), prep, true, nullptr,
-                 &probe);
+    rc = prepare(c, two_j, dl, align_up(adjoint_ring_gbuf_bytes(probe.nd, akl), 256), prep, true,
+                 nullptr, &probe);
     if (rc) return rc;
     RingParams rp = ring_params(prep, B);
     TimedLaunch tl(c, 3);
-    HIP_TRY(c, launch_adjoint_ring(rp, psi, reinterpret_cast<double *>(prep.tail), prep.plan.boff.back(),
-                                   grad_F[0], grad_F[1], grad_boosters, c->stream));
+    HIP_TRY(c, launch_adjoint_ring(rp, akl, aiw, akw, psi, reinterpret_cast<double *>(prep.tail),
+                                   prep.plan.boff.back(), grad_F[0], grad_F[1], grad_boosters, c->stream));
     return EPRL_OK;
   }
   const int kpad = std::max(probe.kmax, 1);
@@ -1277,6 +1506,266 @@ int eprl_contract_boundary_adjoint(eprl_ctx *c, const int two_j[10], int dl, con
   }
   HIP_TRY(c, launch_adjoint_reduce(ap, prep.plan.boff.back(), grad_F[0], grad_F[1], grad_boosters,
                                    c->stream));
+  return EPRL_OK;
+}
+
+int eprl_threejm_batch(eprl_ctx *c, int n, const int *args, double *out) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (n < 0 || (n > 0 && (!args || !out))) return fail(c, EPRL_EINVAL, "invalid arguments");
+  if (n == 0) return EPRL_OK;
+  int big = 0;
+  for (int q = 0; q < n; ++q)
+    for (int a = 0; a < 6; ++a) {
+      const int v = args[6 * q + a];
+      if ((a < 3 && (v < 0 || v > kSixjMaxTwo)) || (a >= 3 && (v < -kSixjMaxTwo || v > kSixjMaxTwo)))
+        return fail(c, EPRL_ERANGE, "3jm argument outside |two_j| <= 200");
+      if (a < 3) big = std::max(big, v);
+    }
+  int rc = ensure_fexp(c, 2 * big + 2);
+  if (rc) return rc;
+  const size_t bytes = (size_t)n * 6 * sizeof(int);
+  rc = ensure_workspace(c, bytes);
+  if (rc) return rc;
+  char *st;
+  rc = staging(c, bytes, &st);
+  if (rc) return rc;
+  std::memcpy(st, args, bytes);
+  rc = upload(c, c->ws, bytes);
+  if (rc) return rc;
+  HIP_TRY(c, launch_threejm_batch(reinterpret_cast<int *>(c->ws), n, out, c->fexp, c->primes,
+                                  c->nprime, c->fact_max, c->stream));
+  return EPRL_OK;
+}
+
+int eprl_boosters(eprl_ctx *c, const int two_j[10], int dl, double gamma, double tol, double *B,
+                  double info[3]) {
+  if (check_ctx(c)) return EPRL_EINVAL;
+  if (!two_j || !B) return fail(c, EPRL_EINVAL, "null argument");
+  if (!(gamma > 0.0) || !std::isfinite(gamma))
+    return fail(c, EPRL_EINVAL, "gamma must be finite and positive");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(c, EPRL_EINVAL, "tol must be finite and positive");
+  Plan p;
+  int rc = make_plan(two_j, dl, p, c->err);
+  if (rc) return rc;
+  std::vector<BoosterBlock> blocks;
+  booster_blocks(p, blocks);
+  const int nb = (int)blocks.size();
+  if (info) info[0] = info[1] = info[2] = 0.0;
+  if (nb == 0) return EPRL_OK;
+  // m-tuples of each edge: m_a in -j_a..j_a (boundary spins), m1 + m2 + m3 + m4 = 0.
+  std::vector<int> mtup;
+  int mt_edge[4], M_edge[4], jb_edge[4][4];
+  for (int e = 0; e < 4; ++e) {
+    int jb[4] = {0, 0, 0, 0};
+    bool found = false;
+    for (const BoosterBlock &b : blocks)
+      if (b.edge == e) {
+        std::copy(b.jb, b.jb + 4, jb);
+        found = true;
+        break;
+      }
+    std::copy(jb, jb + 4, jb_edge[e]);
+    mt_edge[e] = (int)mtup.size();
+    M_edge[e] = 0;
+    if (!found) continue;
+    for (int m1 = -jb[0]; m1 <= jb[0]; m1 += 2)
+      for (int m2 = -jb[1]; m2 <= jb[1]; m2 += 2)
+        for (int m3 = -jb[2]; m3 <= jb[2]; m3 += 2) {
+          const int m4 = -(m1 + m2 + m3);
+          if (m4 < -jb[3] || m4 > jb[3] || ((jb[3] - m4) & 1)) continue;
+          mtup.insert(mtup.end(), {m1, m2, m3, m4});
+          ++M_edge[e];
+        }
+  }
+  // d-function keys: for each (j, l) met on a link, the rows m = -j..j.
+  std::map<std::pair<int, int>, int> key_base;
+  std::vector<DKey> keys;
+  auto key_of = [&](int j2, int l2) {
+    auto it = key_base.find({j2, l2});
+    if (it != key_base.end()) return it->second;
+    const int base = (int)keys.size();
+    key_base[{j2, l2}] = base;
+    const double rho = gamma * (j2 / 2.0 + 1.0);
+    double phase = 0.0;
+    for (int n2 = j2 + 2; n2 <= l2; n2 += 2) phase += std::atan2(rho, n2 / 2.0);
+    phase += 0.5 * 3.14159265358979323846 * ((l2 - j2) / 2);
+    for (int m2 = -j2; m2 <= j2; m2 += 2) {
+      DKey k;
+      k.rho = rho;
+      k.ph_re = std::cos(phase);
+      k.ph_im = -std::sin(phase);
+      k.pre = std::sqrt((j2 + 1.0) * (l2 + 1.0));
+      jacobi_constants(j2, j2, m2, k.nj, k.muj, k.nuj, k.sj);
+      jacobi_constants(l2, j2, m2, k.nl, k.mul, k.nul, k.sl);
+      keys.push_back(k);
+    }
+    return base;
+  };
+  // Per block: edge, idim, kdim, M, m-tuple offset, key bases of its four links; packed and
+  // 4jm-table offsets.  Coefficient sets: the four edges' boundary tables, then every block's.
+  std::vector<int> binfo(9 * (size_t)std::max(nb, 1), 0);
+  std::vector<int64_t> boffs(2 * (size_t)std::max(nb, 1), 0);
+  std::vector<FourjmSet> sets;
+  int64_t ci_edge[4] = {0, 0, 0, 0}, ci_total = 0;
+  int fact = 2;
+  for (int e = 0; e < 4; ++e) {
+    ci_edge[e] = ci_total;
+    const int idim = p.i[e + 1].n, ilo = p.i[e + 1].lo2;
+    if (M_edge[e] == 0) continue;
+    FourjmSet st;
+    std::copy(jb_edge[e], jb_edge[e] + 4, st.j);
+    st.two_lo = ilo;
+    st.n = idim;
+    st.M = M_edge[e];
+    st.mt = mt_edge[e];
+    st.out = ci_total;
+    sets.push_back(st);
+    ci_total += (int64_t)M_edge[e] * idim;
+    const int imax = ilo + 2 * (idim - 1);
+    fact = std::max(fact, std::max(jb_edge[e][0] + jb_edge[e][1], jb_edge[e][2] + jb_edge[e][3]) + imax);
+  }
+  int64_t ck_total = 0, I_total = 0;
+  int Mmax = 0, max_entries = 0;
+  for (const FourjmSet &st : sets) max_entries = std::max(max_entries, st.M * st.n);
+  for (int q = 0; q < nb; ++q) {
+    const BoosterBlock &b = blocks[q];
+    const int M = M_edge[b.edge];
+    int *bi = &binfo[9 * (size_t)q];
+    bi[0] = b.edge;
+    bi[1] = b.idim;
+    bi[2] = b.kdim;
+    bi[3] = M;
+    bi[4] = (int)I_total;
+    for (int a = 0; a < 4; ++a) bi[5 + a] = key_of(b.jb[a], b.lb[a]);
+    boffs[2 * q] = b.off;
+    boffs[2 * q + 1] = ck_total;
+    FourjmSet st;
+    std::copy(b.lb, b.lb + 4, st.j);
+    st.two_lo = b.two_klo;
+    st.n = b.kdim;
+    st.M = M;
+    st.mt = mt_edge[b.edge];
+    st.out = ci_total + ck_total;  // ci and ck share one array
+    sets.push_back(st);
+    max_entries = std::max(max_entries, M * b.kdim);
+    ck_total += (int64_t)M * b.kdim;
+    I_total += M;
+    Mmax = std::max(Mmax, M);
+    const int kmax = b.two_klo + 2 * (b.kdim - 1);
+    fact = std::max(fact, std::max(b.lb[0] + b.lb[1], b.lb[2] + b.lb[3]) + kmax);
+  }
+  if (fact / 2 + 2 > 2 * kSixjMaxTwo + 2) return fail(c, EPRL_ERANGE, "spins beyond the 3jm range");
+  rc = ensure_fexp(c, fact / 2 + 2);
+  if (rc) return rc;
+  const int ns = 256;
+  std::vector<double> sx, sw, gx[2], gw[2];
+  gauss_legendre(ns, sx, sw);
+  gauss_legendre(30, gx[0], gw[0]);
+  gauss_legendre(61, gx[1], gw[1]);
+  const int nkeys = (int)keys.size();
+  // Workspace: the call-independent part first, then the r nodes and the d table (their size
+  // grows with n).
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(std::max<size_t>(bytes, 1), 256);
+    return o;
+  };
+  const size_t o_keys = take(keys.size() * sizeof(DKey));
+  const size_t o_sx = take(ns * sizeof(double)), o_sw = take(ns * sizeof(double));
+  const size_t o_binfo = take(binfo.size() * sizeof(int));
+  const size_t o_boffs = take(boffs.size() * sizeof(int64_t));
+  const size_t o_mt = take(mtup.size() * sizeof(int));
+  const size_t o_sets = take(sets.size() * sizeof(FourjmSet));
+  const size_t static_bytes = off;
+  const size_t o_coef = take((size_t)(ci_total + ck_total) * sizeof(double));
+  const size_t o_I = take((size_t)I_total * 4 * sizeof(double));
+  const size_t o_stat = take((size_t)std::max(nb, 1) * 3 * sizeof(double));
+  const size_t o_stat3 = take(3 * sizeof(double));
+  const size_t o_var = off;
+  const int n_max = 512;
+  char *ws_seen = nullptr;
+  double st3[3] = {0.0, 0.0, 0.0};
+  int n = 16;
+  for (;;) {
+    std::vector<double> r, rw;
+    booster_r_nodes(n, gx, gw, r, rw);
+    const int nr = (int)r.size(), nr30 = 30 * n;
+    off = o_var;
+    const size_t o_r = take(nr * sizeof(double)), o_rw = take(nr * sizeof(double));
+    const size_t o_dtab = take((size_t)nkeys * nr * 2 * sizeof(double));
+    rc = ensure_workspace(c, off);
+    if (rc) return rc;
+    char *ws = c->ws;
+    if (ws != ws_seen) {
+      // (Re)load the call-independent data and the 4jm tables.
+      char *stg;
+      rc = staging(c, static_bytes, &stg);
+      if (rc) return rc;
+      std::memcpy(stg + o_keys, keys.data(), keys.size() * sizeof(DKey));
+      std::memcpy(stg + o_sx, sx.data(), ns * sizeof(double));
+      std::memcpy(stg + o_sw, sw.data(), ns * sizeof(double));
+      std::memcpy(stg + o_binfo, binfo.data(), binfo.size() * sizeof(int));
+      std::memcpy(stg + o_boffs, boffs.data(), boffs.size() * sizeof(int64_t));
+      if (!mtup.empty()) std::memcpy(stg + o_mt, mtup.data(), mtup.size() * sizeof(int));
+      if (!sets.empty()) std::memcpy(stg + o_sets, sets.data(), sets.size() * sizeof(FourjmSet));
+      rc = upload(c, ws, static_bytes);
+      if (rc) return rc;
+      HIP_TRY(c, launch_fourjm_tables(reinterpret_cast<const FourjmSet *>(ws + o_sets), (int)sets.size(),
+                                      max_entries, reinterpret_cast<const int *>(ws + o_mt),
+                                      reinterpret_cast<double *>(ws + o_coef), c->fexp, c->primes,
+                                      c->nprime, c->stream));
+      ws_seen = ws;
+    }
+    {
+      char *stg;
+      rc = staging(c, 2 * align_up(nr * sizeof(double), 256), &stg);
+      if (rc) return rc;
+      std::memcpy(stg, r.data(), nr * sizeof(double));
+      std::memcpy(stg + (o_rw - o_r), rw.data(), nr * sizeof(double));
+      rc = upload(c, ws + o_r, o_dtab - o_r);
+      if (rc) return rc;
+    }
+    BoosterParams bp;
+    std::memset(&bp, 0, sizeof(bp));
+    bp.keys = reinterpret_cast<const DKey *>(ws + o_keys);
+    bp.nkeys = nkeys;
+    bp.sx = reinterpret_cast<const double *>(ws + o_sx);
+    bp.sw = reinterpret_cast<const double *>(ws + o_sw);
+    bp.ns = ns;
+    bp.r = reinterpret_cast<const double *>(ws + o_r);
+    bp.rw = reinterpret_cast<const double *>(ws + o_rw);
+    bp.nr = nr;
+    bp.nr30 = nr30;
+    bp.dtab = reinterpret_cast<double *>(ws + o_dtab);
+    bp.binfo = reinterpret_cast<const int *>(ws + o_binfo);
+    bp.boffs = reinterpret_cast<const int64_t *>(ws + o_boffs);
+    bp.mtuples = reinterpret_cast<const int *>(ws + o_mt);
+    for (int e = 0; e < 4; ++e) {
+      bp.mt_edge[e] = mt_edge[e];
+      bp.ci_edge[e] = ci_edge[e];
+      for (int a = 0; a < 4; ++a) bp.jb_edge[e][a] = jb_edge[e][a];
+    }
+    bp.ci = reinterpret_cast<const double *>(ws + o_coef);
+    bp.ck = reinterpret_cast<const double *>(ws + o_coef) + ci_total;
+    bp.I = reinterpret_cast<double *>(ws + o_I);
+    bp.B = B;
+    bp.stat = reinterpret_cast<double *>(ws + o_stat);
+    bp.nblocks = nb;
+    bp.Mmax = Mmax;
+    HIP_TRY(c, launch_booster_dfun(bp, c->stream));
+    HIP_TRY(c, launch_booster_integrals(bp, c->stream));
+    HIP_TRY(c, launch_booster_assemble(bp, reinterpret_cast<double *>(ws + o_stat3), c->stream));
+    HIP_TRY(c, hipMemcpyAsync(st3, ws + o_stat3, sizeof(st3), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (st3[0] <= tol * std::max(st3[1], 1e-300) || n >= n_max) break;
+    n *= 2;
+  }
+  if (info) {
+    info[0] = st3[0];
+    info[1] = st3[2];
+    info[2] = n;
+  }
   return EPRL_OK;
 }
 

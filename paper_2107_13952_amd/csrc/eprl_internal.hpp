@@ -143,9 +143,13 @@ size_t wide_smem_bytes(int nd, const int i_n[5], int kw, int nrb, bool stg);
 int wide_row_blocks(const int i_n[5]);
 bool wide_fits(int nd, const int i_n[5], int kw, int nrb, bool stg = false);
 hipError_t wide_init_attributes();
-hipError_t launch_wide(const RingParams &rp, hipStream_t s);
-hipError_t launch_wide_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems,
-                             size_t smem, bool stg, int grid, int *next, hipStream_t s);
+// Plain call, persistent (one workgroup per CU, ncu of them at most); next: eight device ints
+// of scratch for the per-XCD counters (reset by the launch).
+hipError_t launch_wide(const RingParams &rp, int *next, int ncu, hipStream_t s);
+// Persistent launch over per-XCD item lists: list x is items [xoff[x], xoff[x + 1]) of
+// items_dev (offsets relative to items_dev, device memory), next[0..7] its counters (zeroed).
+hipError_t launch_wide_batch(const RingParams *cfgs_dev, const int *items_dev, const int *xoff_dev,
+                             int nitems, size_t smem, bool stg, int grid, int *next, hipStream_t s);
 // Splits the cores of the factorised path, for each i1, into chunks of equal estimated cost
 // (x iterations plus the per-core set-up), about target_wg workgroups in all and at most
 // kRingMaxPartialBytes of partial sums; fills bounds ([i1][nchunk + 1]) and, if asked for, the
@@ -190,6 +194,81 @@ hipError_t contract_scratch_address(double **ptr);
 hipError_t launch_grad_psi(const ContractParams &cp, double gre, double gim, double *const out[5],
                            hipStream_t s);
 
+// Booster builder (boosters.hip; 4jm coefficient tables in sixj.hip).
+// One booster block: edge e (0..3 for edges 2..5), boundary and virtual spins of its four links
+// (two-units, pairing (first second)(third fourth)), intertwiner ranges, packed offset.
+struct BoosterBlock {
+  int edge;
+  int jb[4], lb[4];
+  int two_ilo, idim, two_klo, kdim;
+  int64_t off;
+};
+void booster_blocks(const Plan &p, std::vector<BoosterBlock> &out);
+// A table of 4jm coefficients: out[o + m n + i] = 4jm(j; m-tuple m; two_lo + 2 i) for the M
+// m-tuples at mtuples[mt + 4 m ..].
+struct FourjmSet {
+  int j[4];
+  int two_lo, n;
+  int M, mt;
+  int64_t out;
+};
+hipError_t launch_fourjm_tables(const FourjmSet *sets_dev, int nsets, int max_entries,
+                                const int *mtuples_dev, double *out, const uint16_t *fexp,
+                                const int *primes, int nprime, hipStream_t s);
+hipError_t launch_threejm_batch(const int *args, int n, double *out, const uint16_t *fexp,
+                                const int *primes, int nprime, int fact_max, hipStream_t s);
+// A boost matrix element d^{(rho, k = j)}_{j l m}(r): spins, the Y-map rho = gamma (j + 1), the
+// phase factor of the basis convention, and the Jacobi-form constants of the two SU(2) d
+// functions it integrates, d^j_{j m} and d^l_{j m}.
+struct DKey {
+  double rho, ph_re, ph_im, pre;      // pre = sqrt((2j+1)(2l+1))
+  double nj, nl;                      // xi * sqrt(s! (s+mu+nu)! / ((s+mu)! (s+nu)!)) of each d
+  int muj, nuj, sj, mul, nul, sl;     // Jacobi parameters of each d
+};
+struct BoosterParams {
+  const DKey *keys;
+  int nkeys;
+  const double *sx, *sw;   // Gauss-Legendre nodes and weights of the s integral on [-1, 1]
+  int ns;
+  const double *r, *rw;    // r nodes (30-point rule, then 61-point rule) and their weights,
+  int nr, nr30;            //   rw including sinh^2 r / (4 pi) and the Jacobian of u = e^{-r}
+  double *dtab;            // complex [key][r]
+  // blocks
+  const int *binfo;        // per block: edge, idim, kdim, M, moff, kb[4]  (9 ints)
+  const int64_t *boffs;    // per block: packed offset, ck offset
+  const int *mtuples;      // per edge: its m-tuples (4 ints each), edge e at mt_edge[e]
+  int mt_edge[4];
+  int jb_edge[4][4];       // boundary spins of each edge's four links
+  const double *ci;        // per edge: M x idim 4jm of the boundary spins, edge e at ci_edge[e]
+  int64_t ci_edge[4];
+  const double *ck;        // per block: M x kdim 4jm of the virtual spins
+  double *I;               // per block and m-tuple: the two rules' integrals, complex (4 doubles)
+  double *B;               // packed boosters (real parts of the 61-point values)
+  double *stat;            // per block: max |G61 - G30|, max |G61|, max |Im G61|
+  int nblocks, Mmax;
+};
+hipError_t launch_booster_dfun(const BoosterParams &bp, hipStream_t s);
+hipError_t launch_booster_integrals(const BoosterParams &bp, hipStream_t s);
+hipError_t launch_booster_assemble(const BoosterParams &bp, double *stat3, hipStream_t s);
+
+// Multi-vertex contractions (network.hip).
+struct TrailParams {
+  const double *A;        // [lead][S] row-major
+  int m;                  // trailing intertwiners contracted
+  int n[5];               // their dimensions
+  const double *psi[5];   // their vectors (complex)
+  int64_t S;              // prod n[0..m-1]
+  int nsplit;             // blocks per leading row
+  double *T;              // complex [lead]
+  double *partial;        // complex [lead][nsplit] when nsplit > 1
+};
+hipError_t launch_contract_vertices(const double *A, const double *B, int64_t total, int nblocks,
+                                    double *partial, double *F, hipStream_t s);
+int trailing_splits(int64_t nlead, int64_t S);
+hipError_t launch_contract_trailing(const TrailParams &tp, int64_t nlead, hipStream_t s);
+hipError_t launch_delta3(int n, int two_klo, int two_x, const double *TA, const double *TB,
+                         const double *TC, double *F, hipStream_t s);
+
 struct AdjointParams {
   VertexParams v;
   const double *psi[5];
@@ -201,11 +280,16 @@ hipError_t launch_adjoint_shells(const AdjointParams &ap, hipStream_t s);
 // entry of `total`); the per-core G vectors go to gbuf (adjoint_ring_gbuf_bytes).  Applies where
 // the factorised vertex kernels do, with dl + 1 <= kAdjRingMaxNd.
 constexpr int kAdjRingMaxNd = 11;
-size_t adjoint_ring_smem(int nd);
-size_t adjoint_ring_gbuf_bytes(int nd);
+constexpr size_t kAdjRingMaxLds = 160 * 1024 - 256;
+// LDS sizes of the kernel for a configuration: kl = largest k range of a spin, iw = number of i1
+// values, kw = widest core window of k5, k4 (over l45), k3 or k2 (over l23).
+void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw);
+size_t adjoint_ring_smem(int nd, int kl, int iw, int kw);
+size_t adjoint_ring_gbuf_bytes(int nd, int kl);
 hipError_t adjoint_ring_init_attributes();
-hipError_t launch_adjoint_ring(const RingParams &rp, const double *const psi[5], double *gbuf,
-                               int64_t total, double gre, double gim, double *grad_b, hipStream_t s);
+hipError_t launch_adjoint_ring(const RingParams &rp, int kl, int iw, int kw, const double *const psi[5],
+                               double *gbuf, int64_t total, double gre, double gim, double *grad_b,
+                               hipStream_t s);
 hipError_t launch_adjoint_reduce(const AdjointParams &ap, int64_t total, double gre, double gim,
                                  double *grad_b, hipStream_t s);
 

@@ -277,8 +277,18 @@ int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds,
   }
   bounds.assign((size_t)d1 * (nchunk + 1), 0);
   if (chunk_cost) chunk_cost->assign((size_t)d1 * nchunk, 0.0);
+  // The wide kernel splits the cores the same way for every i1 (by the cost summed over i1):
+  // the work items of one chunk then read the same 6j table slices and booster blocks, which
+  // the XCD-aware launch order keeps in one L2.
+  const bool shared = p.ring_cls == kWideClass;
+  std::vector<double> sum_cost;
+  if (shared) {
+    sum_cost.assign(ncore, 0.0);
+    for (int n1 = 0; n1 < d1; ++n1)
+      for (int k = core_lo; k < core_hi; ++k) sum_cost[k] += cost[(size_t)n1 * ncore + k];
+  }
   for (int n1 = 0; n1 < d1; ++n1) {
-    const double *cs = cost.data() + (size_t)n1 * ncore;
+    const double *cs = shared ? sum_cost.data() : cost.data() + (size_t)n1 * ncore;
     double total = 0.0;
     for (int k = core_lo; k < core_hi; ++k) total += cs[k];
     int *bd = bounds.data() + (size_t)n1 * (nchunk + 1);
@@ -293,7 +303,8 @@ int ring_schedule(const Plan &p, int target_wg, std::vector<int> &bounds,
     bd[nchunk] = core_hi;
     if (chunk_cost)
       for (int ch = 0; ch < nchunk; ++ch)
-        for (int q = bd[ch]; q < bd[ch + 1]; ++q) (*chunk_cost)[(size_t)n1 * nchunk + ch] += cs[q];
+        for (int q = bd[ch]; q < bd[ch + 1]; ++q)
+          (*chunk_cost)[(size_t)n1 * nchunk + ch] += cost[(size_t)n1 * ncore + q];
   }
   return nchunk;
 }
@@ -471,6 +482,36 @@ void count_work(const Plan &p, double out[5]) {
   out[2] = useful;
   out[3] = executed;
   out[4] = p.ring_cls;
+}
+
+// Booster blocks of a configuration in packing order (eq. (booster); edges 2..5, offset
+// triples of their virtual links): the boundary and virtual spins of the edge's four links,
+// the intertwiner ranges and the block's offset in the packed buffer.  Empty blocks are left out.
+void booster_blocks(const Plan &p, std::vector<BoosterBlock> &out) {
+  out.clear();
+  const int nd = p.nd, nd3 = nd * nd * nd;
+  for (int e = 0; e < 4; ++e)
+    for (int t = 0; t < nd3; ++t) {
+      const int kn = p.kr[(e * nd3 + t) * 2 + 1];
+      if (kn == 0 || p.i[e + 1].n == 0) continue;
+      const int o[3] = {t / (nd * nd), (t / nd) % nd, t % nd};
+      int l[10];
+      for (int n = 0; n < 10; ++n) l[n] = p.two_j[n];
+      for (int q = 0; q < 3; ++q) l[kEdgeTriple[e][q]] += 2 * o[q];
+      BoosterBlock b;
+      b.edge = e;
+      const int *L = kEdgeLinks[e + 1];
+      for (int a = 0; a < 4; ++a) {
+        b.jb[a] = p.two_j[L[a]];
+        b.lb[a] = l[L[a]];
+      }
+      b.two_ilo = p.i[e + 1].lo2;
+      b.idim = p.i[e + 1].n;
+      b.two_klo = p.kr[(e * nd3 + t) * 2];
+      b.kdim = kn;
+      b.off = p.boff[(size_t)e * nd3 + t];
+      out.push_back(b);
+    }
 }
 
 }  // namespace eprl

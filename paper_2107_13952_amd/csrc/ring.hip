@@ -588,7 +588,7 @@ __global__ __launch_bounds__(RT, (ring_waves<DI, DK, KW>())) void ring_batch_ker
 
 // Resets the work-queue counters of a batch (a kernel, so that graph replays start from 0).
 __global__ void reset_counters(int *c, int n) {
-  if (threadIdx.x < n) c[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
 }
 
 template <int DI, int DK, int KW, int STG>

@@ -181,6 +181,109 @@ __device__ double sixj_device(int a, int b, int c, int d, int e, int f, const ui
   return (tmin & 1) ? -r : r;
 }
 
+// Wigner 3jm symbol (j1 j2 j3; m1 m2 m3), arguments in two-units, by Racah's single sum
+//   (-1)^(j1-j2-m3) sqrt(D(j1 j2 j3) prod_a (j_a+m_a)! (j_a-m_a)!)
+//     * sum_t (-1)^t / [t! (j3-j2+t+m1)! (j3-j1+t-m2)! (j1+j2-j3-t)! (j1-t-m1)! (j2-t+m2)!],
+// D(abc) = (a+b-c)! (a-b+c)! (-a+b+c)! / (a+b+c+1)!, evaluated like the 6j symbol above: the
+// common factor sqrt(D prod (j +- m)!) T0 as an exact square root from prime exponents, the
+// series 1 + r_0 + r_0 r_1 + ... with exact integer ratios in double-double.
+__device__ double threejm_device(int j1, int j2, int j3, int m1, int m2, int m3, const uint16_t *fexp,
+                                 const int *primes, int nprime) {
+  if (m1 + m2 + m3 != 0 || !triad_ok(j1, j2, j3)) return 0.0;
+  const int jj[3] = {j1, j2, j3}, mm[3] = {m1, m2, m3};
+  for (int q = 0; q < 3; ++q)
+    if (mm[q] > jj[q] || -mm[q] > jj[q] || ((jj[q] - mm[q]) & 1)) return 0.0;
+  // Integer (not two-unit) quantities.
+  const int a1 = (j1 + j2 - j3) / 2, a2 = (j1 - m1) / 2, a3 = (j2 + m2) / 2;   // (. - t)!
+  const int b1 = (j3 - j2 + m1) / 2, b2 = (j3 - j1 - m2) / 2;                   // (. + t)!
+  int tmin = 0, tmax = a1;
+  if (-b1 > tmin) tmin = -b1;
+  if (-b2 > tmin) tmin = -b2;
+  if (a2 < tmax) tmax = a2;
+  if (a3 < tmax) tmax = a3;
+  if (tmin > tmax) return 0.0;
+  int arg[16], coef[16];
+  int na = 0;
+  arg[na] = (j1 + j2 - j3) / 2; coef[na++] = 1;
+  arg[na] = (j1 - j2 + j3) / 2; coef[na++] = 1;
+  arg[na] = (-j1 + j2 + j3) / 2; coef[na++] = 1;
+  arg[na] = (j1 + j2 + j3) / 2 + 1; coef[na++] = -1;
+  for (int q = 0; q < 3; ++q) {
+    arg[na] = (jj[q] + mm[q]) / 2; coef[na++] = 1;
+    arg[na] = (jj[q] - mm[q]) / 2; coef[na++] = 1;
+  }
+  arg[na] = tmin; coef[na++] = -2;
+  arg[na] = b1 + tmin; coef[na++] = -2;
+  arg[na] = b2 + tmin; coef[na++] = -2;
+  arg[na] = a1 - tmin; coef[na++] = -2;
+  arg[na] = a2 - tmin; coef[na++] = -2;
+  arg[na] = a3 - tmin; coef[na++] = -2;
+  const int top = (j1 + j2 + j3) / 2 + 1;
+  dde num{0.5, 0.0, 1}, den{0.5, 0.0, 1};
+  for (int ip = 0; ip < nprime; ++ip) {
+    const int pr = primes[ip];
+    if (pr > top) break;
+    int E = 0;
+    for (int q = 0; q < na; ++q) E += coef[q] * (int)fexp[arg[q] * nprime + ip];
+    if (E == 0) continue;
+    dd sp = dd_sqrt_int((double)pr);
+    if (E > 0)
+      num = dde_mul(num, dde_pow(sp, E));
+    else
+      den = dde_mul(den, dde_pow(sp, -E));
+  }
+  // term(t+1) / term(t) = -(a1 - t)(a2 - t)(a3 - t) / ((t + 1)(b1 + t + 1)(b2 + t + 1))
+  dd rho{1.0, 0.0}, sum{1.0, 0.0};
+  for (int t = tmin; t < tmax; ++t) {
+    const double nu = -(double)(a1 - t) * (double)(a2 - t) * (double)(a3 - t);
+    const double de = (double)(t + 1) * (double)(b1 + t + 1) * (double)(b2 + t + 1);
+    rho = dd_mul(rho, dd_ratio(nu, de));
+    sum = dd_add(sum, rho);
+  }
+  dd q;
+  {
+    double qh = num.hi / den.hi;
+    dd prod = dd_mul({qh, 0.0}, {den.hi, den.lo});
+    dd diff = dd_add({num.hi, num.lo}, {-prod.hi, -prod.lo});
+    q = fast_two_sum(qh, diff.hi / den.hi);
+  }
+  dd v = dd_mul(q, sum);
+  const double r = __builtin_ldexp(v.hi + v.lo, num.e - den.e);
+  const int ph = (j1 - j2 - m3) / 2 + tmin;
+  return (ph & 1) ? -r : r;
+}
+
+// 4jm(j1 j2 j3 j4; m1 m2 m3 m4)^(i): (j1 j2) coupled to i, then i with (j3 j4),
+//   (-1)^(i - mi) (j1 j2 i; m1 m2 mi) (i j3 j4; -mi m3 m4),  mi = -(m1 + m2).
+__device__ double fourjm_device(const int *j, const int *m, int i, const uint16_t *fexp,
+                                const int *primes, int nprime) {
+  const int mi = -(m[0] + m[1]);
+  if (mi - m[2] - m[3] != 0) return 0.0;
+  const double v = threejm_device(j[0], j[1], i, m[0], m[1], mi, fexp, primes, nprime) *
+                   threejm_device(i, j[2], j[3], -mi, m[2], m[3], fexp, primes, nprime);
+  return (((i - mi) / 2) & 1) ? -v : v;
+}
+
+// Coefficient tables of the booster contraction: set s (blockIdx.y), entry (m, i) of its
+// M x n table = 4jm(j; m-tuple m; two_lo + 2 i).
+__global__ void fourjm_table_kernel(const FourjmSet *sets, const int *mtuples, double *out,
+                                    const uint16_t *fexp, const int *primes, int nprime) {
+  const FourjmSet st = sets[blockIdx.y];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= st.M * st.n) return;
+  const int m = idx / st.n, i = idx % st.n;
+  out[st.out + idx] = fourjm_device(st.j, mtuples + st.mt + 4 * m, st.two_lo + 2 * i, fexp, primes,
+                                    nprime);
+}
+
+__global__ void threejm_batch_kernel(const int *args, int n, double *out, const uint16_t *fexp,
+                                     const int *primes, int nprime, int fact_max) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int *a = args + 6 * idx;
+  out[idx] = threejm_device(a[0], a[1], a[2], a[3], a[4], a[5], fexp, primes, nprime);
+}
+
 __global__ void fexp_kernel(uint16_t *fexp, int fact_max, const int *primes, int nprime) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (fact_max + 1) * nprime) return;
@@ -360,6 +463,22 @@ hipError_t launch_sixj_tables(const TableParams &tp, int64_t total, hipStream_t 
 hipError_t launch_ring_tables(const TableParams &tp, int64_t total, hipStream_t s) {
   int64_t blocks = (total + 255) / 256;
   ring_table_kernel<<<(unsigned)blocks, 256, 0, s>>>(tp, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_fourjm_tables(const FourjmSet *sets_dev, int nsets, int max_entries,
+                                const int *mtuples_dev, double *out, const uint16_t *fexp,
+                                const int *primes, int nprime, hipStream_t s) {
+  if (nsets <= 0 || max_entries <= 0) return hipSuccess;
+  dim3 grid((unsigned)((max_entries + 255) / 256), (unsigned)nsets);
+  fourjm_table_kernel<<<grid, 256, 0, s>>>(sets_dev, mtuples_dev, out, fexp, primes, nprime);
+  return hipGetLastError();
+}
+
+hipError_t launch_threejm_batch(const int *args, int n, double *out, const uint16_t *fexp,
+                                const int *primes, int nprime, int fact_max, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  threejm_batch_kernel<<<(n + 255) / 256, 256, 0, s>>>(args, n, out, fexp, primes, nprime, fact_max);
   return hipGetLastError();
 }
 

@@ -400,33 +400,71 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
   __syncthreads();  // the next item reuses the LDS
 }
 
-template <bool STG>
-__global__ __launch_bounds__(WT, 1) void wide_kernel(RingParams rp) {
-  extern __shared__ double smem[];
-  wide_item<STG>(rp, blockIdx.x, blockIdx.y, blockIdx.z, smem);
-}
+// Workgroups are dispatched to the eight XCDs round-robin (workgroup b on XCD b % 8; checked on
+// the device against the XCC_ID hardware register, which the kernels read).  The persistent
+// kernels give each XCD its own lists of work items so that the items of one chunk of cores, all
+// (i1, row block) of it, run on one XCD one after the other: with the chunk bounds shared by
+// every i1, those items read the same 6j table slices and booster blocks, which then stay in
+// that XCD's L2.
+// XCD this workgroup runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7; }
 
-// Persistent variant for batches: workgroups take (configuration, chunk, i1, row block) items of
-// a longest-first list from a counter; every item writes its own partial slice, so which
-// workgroup runs it does not matter.  The loop ends for every workgroup once the counter
-// passes nitems.
+// Plain call, persistent: XCD x owns the chunks c with c % 8 == x, item j of its list being
+// chunk (j / (d1 nrb)) * 8 + x, i1 and row block from j % (d1 nrb).  A workgroup takes items
+// from its own XCD's list through that list's counter (next[x], zeroed before the launch), then
+// from the other lists in turn; every item writes its own partial slice, so which workgroup runs
+// it does not matter.  The loop ends for every workgroup once all eight counters have passed the
+// ends of their lists.
 template <bool STG>
-__global__ __launch_bounds__(WT, 1) void wide_batch_kernel(const RingParams *cfgs, const int *items,
-                                                          int nitems, int *next) {
+__global__ __launch_bounds__(WT, 1) void wide_kernel(RingParams rp, int *next) {
   extern __shared__ double smem[];
   __shared__ int it_s;
-  for (;;) {
-    if (threadIdx.x == 0) it_s = atomicAdd(next, 1);
-    __syncthreads();
-    // The item and its fields are the same for the whole workgroup: read them through scalar
-    // registers, so that the configuration's parameters are scalar loads too.
-    const int it = __builtin_amdgcn_readfirstlane(it_s);
-    __syncthreads();
-    if (it >= nitems) break;
-    const int *p = items + 4 * it;
-    const int q0 = __builtin_amdgcn_readfirstlane(p[0]), q1 = __builtin_amdgcn_readfirstlane(p[1]);
-    const int q2 = __builtin_amdgcn_readfirstlane(p[2]), q3 = __builtin_amdgcn_readfirstlane(p[3]);
-    wide_item<STG>(cfgs[q0], q1, q2, q3, smem);
+  const int per_chunk = rp.i_n[0] * rp.nrb;
+  const int home = xcc_id();
+  for (int v = 0; v < 8; ++v) {
+    const int qx = (home + v) & 7;
+    const int n = (qx < rp.nchunk ? (rp.nchunk - qx + 7) / 8 : 0) * per_chunk;
+    for (;;) {
+      if (threadIdx.x == 0) it_s = atomicAdd(next + qx, 1);
+      __syncthreads();
+      const int it = __builtin_amdgcn_readfirstlane(it_s);
+      __syncthreads();
+      if (it >= n) break;
+      const int chunk = (it / per_chunk) * 8 + qx, r = it % per_chunk;
+      wide_item<STG>(rp, chunk, r / rp.nrb, r % rp.nrb, smem);
+    }
+  }
+}
+
+// Persistent variant for batches: the (configuration, chunk, i1, row block) items are split into
+// eight lists, one per XCD (whole chunks per list, balanced by cost, longest chunks first, the
+// items of a chunk together), list x holding items [xoff[x], xoff[x + 1]).  A workgroup takes
+// items from its own XCD's list through that list's counter, then from the other lists in turn;
+// every item writes its own partial slice, so which workgroup runs it does not matter.  The loop
+// ends for every workgroup once all eight counters have passed the ends of their lists.
+template <bool STG>
+__global__ __launch_bounds__(WT, 1) void wide_batch_kernel(const RingParams *cfgs, const int *items,
+                                                          const int *xoff, int *next) {
+  extern __shared__ double smem[];
+  __shared__ int it_s;
+  const int home = xcc_id();
+  for (int v = 0; v < 8; ++v) {
+    const int qx = (home + v) & 7;
+    const int lo = __builtin_amdgcn_readfirstlane(xoff[qx]);
+    const int n = __builtin_amdgcn_readfirstlane(xoff[qx + 1]) - lo;
+    for (;;) {
+      if (threadIdx.x == 0) it_s = atomicAdd(next + qx, 1);
+      __syncthreads();
+      // The item and its fields are the same for the whole workgroup: read them through scalar
+      // registers, so that the configuration's parameters are scalar loads too.
+      const int it = __builtin_amdgcn_readfirstlane(it_s);
+      __syncthreads();
+      if (it >= n) break;
+      const int *p = items + 4 * (lo + it);
+      const int q0 = __builtin_amdgcn_readfirstlane(p[0]), q1 = __builtin_amdgcn_readfirstlane(p[1]);
+      const int q2 = __builtin_amdgcn_readfirstlane(p[2]), q3 = __builtin_amdgcn_readfirstlane(p[3]);
+      wide_item<STG>(cfgs[q0], q1, q2, q3, smem);
+    }
   }
 }
 
@@ -458,22 +496,26 @@ hipError_t wide_init_attributes() {
   return hipSuccess;
 }
 
-hipError_t launch_wide(const RingParams &rp, hipStream_t s) {
-  dim3 grid(rp.nchunk, rp.i_n[0], rp.nrb);
+hipError_t launch_wide(const RingParams &rp, int *next, int ncu, hipStream_t s) {
+  const int items = rp.nchunk * rp.i_n[0] * rp.nrb;
+  const unsigned grid = (unsigned)(items < ncu ? items : ncu);
+  if (grid == 0) return hipSuccess;
+  hipError_t e = launch_reset_counters(next, 8, s);
+  if (e != hipSuccess) return e;
   if (wide_fits(rp.nd, rp.i_n, rp.kw, rp.nrb, true))
-    wide_kernel<true><<<grid, WT, wide_bytes(rp.nd, rp.i_n, rp.kw, rp.nrb, true), s>>>(rp);
+    wide_kernel<true><<<grid, WT, wide_bytes(rp.nd, rp.i_n, rp.kw, rp.nrb, true), s>>>(rp, next);
   else
-    wide_kernel<false><<<grid, WT, wide_bytes(rp.nd, rp.i_n, rp.kw, rp.nrb, false), s>>>(rp);
+    wide_kernel<false><<<grid, WT, wide_bytes(rp.nd, rp.i_n, rp.kw, rp.nrb, false), s>>>(rp, next);
   return hipGetLastError();
 }
 
-hipError_t launch_wide_batch(const RingParams *cfgs_dev, const int *items_dev, int nitems,
-                             size_t smem, bool stg, int grid, int *next, hipStream_t s) {
+hipError_t launch_wide_batch(const RingParams *cfgs_dev, const int *items_dev, const int *xoff_dev,
+                             int nitems, size_t smem, bool stg, int grid, int *next, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   if (stg)
-    wide_batch_kernel<true><<<grid, WT, smem, s>>>(cfgs_dev, items_dev, nitems, next);
+    wide_batch_kernel<true><<<grid, WT, smem, s>>>(cfgs_dev, items_dev, xoff_dev, next);
   else
-    wide_batch_kernel<false><<<grid, WT, smem, s>>>(cfgs_dev, items_dev, nitems, next);
+    wide_batch_kernel<false><<<grid, WT, smem, s>>>(cfgs_dev, items_dev, xoff_dev, next);
   return hipGetLastError();
 }
 

@@ -7,8 +7,9 @@ intertwiner range is asked for) and A[rows, i2..i5] (float64).  Entries with phy
 (booster_seed -1).  The shell sum is split over worker
 processes by contiguous shell ranges and the partial tensors are summed in range order.
 
-    python tests/golden/make_golden.py               # every entry of GOLDEN (about 30 min, 8 cores)
+    python tests/golden/make_golden.py               # every entry (about 35 min, 8 cores)
     python tests/golden/make_golden.py j3_dl8 ...     # the named entries only
+    python tests/golden/make_golden.py irr_a irr_b    # the booster-only entries
 """
 import os
 import sys
@@ -62,6 +63,14 @@ def _registry():
 
 GOLDEN = _registry()
 
+# Boosters alone (the oracle's FP64 quadrature of eq. (booster) at gamma = 1.2), for the parity of
+# the device booster builder on irregular spins: ``boosters_<name>.npz`` with the spins, dl,
+# gamma and the packed boosters.
+BOOSTER_GOLDEN = {"irr_a": ([4, 1, 1, 4, 4, 3, 3, 1, 4, 1], 1),
+                  "irr_b": ([2, 3, 2, 1, 3, 2, 3, 1, 1, 3], 1),
+                  # configuration 0 of the large-spin batch (spins 5..7) at dl = 0
+                  "b5_c00_dl0": (list(W.cfg5_batch()[0][0]), 0)}
+
 
 def _part(args):
     two_j, dl, b, rows, lo, hi = args
@@ -93,8 +102,18 @@ def make(name, procs=8, pieces=64):
     return out
 
 
+def make_boosters(name):
+    two_j, dl = BOOSTER_GOLDEN[name]
+    b, imag, err = B.boosters(two_j, dl, GAMMA)
+    assert imag <= 1e-14 * np.abs(b).max() and err <= 1e-13 * np.abs(b).max(), (imag, err)
+    out = os.path.join(HERE, f"boosters_{name}.npz")
+    np.savez_compressed(out, two_j=np.array(two_j), dl=dl, gamma=GAMMA, boosters=b)
+    return out
+
+
 if __name__ == "__main__":
-    names = sys.argv[1:] or list(GOLDEN)
+    names = sys.argv[1:] or list(GOLDEN) + list(BOOSTER_GOLDEN)
     for nm in names:
         t = time.time()
-        print(make(nm), f"{time.time() - t:.0f} s", flush=True)
+        path = make_boosters(nm) if nm in BOOSTER_GOLDEN else make(nm)
+        print(path, f"{time.time() - t:.0f} s", flush=True)
