@@ -46,7 +46,7 @@ __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
-constexpr int AT = 256;  // threads per workgroup
+constexpr int AT = 512;  // threads per workgroup
 
 // The five boundary vectors (device, complex interleaved), passed by value.
 struct PsiPtrs {
