@@ -54,24 +54,26 @@ struct PsiPtrs {
 };
 // LDS layout (complex unless noted), sized by the configuration: kl = largest k range of a spin,
 // iw = number of i1 values, kw = widest core window of k5, k4, k3 or k2 (union over l45 or l23).
-// Per-spin arrays are [nd][kl].  R3 reuses X2 (dead once R4 is formed) and S2 reuses Z5 (dead
-// after the left half).
+// Per-spin arrays are [nd][kl].  The two halves take their spins (l45, then l23) ng at a time,
+// Z5, Q5 and S2 holding one [iw][kl] / [kl][iw] block per spin of the group.  R3 reuses X2 (dead
+// once R4 is formed) and S2 reuses Z5 (dead after the left half).
 struct AdjGeom {
-  int kl, iw, kw;
+  int kl, iw, kw, ng;
   int p1, u5, u4, u2, u3, g5, g4, g3, g2;     // [iw] and [nd][kl] vectors
   int v2;                                      // [nd][kl k3][iw]
   int x2, r4, x5, r3;                          // [kw][iw] or [iw][kw]
-  int z5, q5, s2;                              // [iw][kl], [kl][iw], [iw][kl] scratch
+  int z5, q5, s2;                              // [ng][iw][kl], [ng][kl][iw], [ng][iw][kl] scratch
   int u1s, u5s, u3s;                           // real: [iw][kw], [kw][iw], [kw][kw]
   int meta;                                    // ints: rng [8][nd], then int64 bo [4][nd]
   size_t bytes;
 };
 
-__host__ __device__ inline AdjGeom adj_geom(int nd, int kl, int iw, int kw) {
+__host__ __device__ inline AdjGeom adj_geom(int nd, int kl, int iw, int kw, int ng) {
   AdjGeom g;
   g.kl = kl;
   g.iw = iw;
   g.kw = kw;
+  g.ng = ng;
   int c = 0;  // in complex units (16 bytes)
   g.p1 = c; c += iw;
   g.u5 = c; c += nd * kl;
@@ -87,8 +89,8 @@ __host__ __device__ inline AdjGeom adj_geom(int nd, int kl, int iw, int kw) {
   g.r4 = c; c += kw * iw;
   g.x5 = c; c += iw * kw;
   g.r3 = g.x2;
-  g.z5 = c; c += iw * kl;
-  g.q5 = c; c += kl * iw;
+  g.z5 = c; c += ng * iw * kl;
+  g.q5 = c; c += ng * kl * iw;
   g.s2 = g.z5;
   int d = 2 * c;  // in doubles
   g.u1s = d; d += iw * kw;
@@ -100,11 +102,11 @@ __host__ __device__ inline AdjGeom adj_geom(int nd, int kl, int iw, int kw) {
 }
 
 __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs psi, double *gbuf,
-                                                          int KLr, int IWr, int KWr) {
+                                                          int KLr, int IWr, int KWr, int NGr) {
   extern __shared__ double sm[];
   const int nd = rp.nd, nd3 = nd * nd * nd;
-  const AdjGeom geo = adj_geom(nd, KLr, IWr, KWr);
-  const int kl = geo.kl, iw = geo.iw, kw = geo.kw;
+  const AdjGeom geo = adj_geom(nd, KLr, IWr, KWr, NGr);
+  const int kl = geo.kl, iw = geo.iw, kw = geo.kw, ng = geo.ng;
   cplx *cs = reinterpret_cast<cplx *>(sm);
   cplx *P1 = cs + geo.p1, *u5 = cs + geo.u5, *u4 = cs + geo.u4, *u2 = cs + geo.u2, *u3 = cs + geo.u3;
   cplx *G5 = cs + geo.g5, *G4 = cs + geo.g4, *G3 = cs + geo.g3, *G2 = cs + geo.g2;
@@ -262,54 +264,65 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
       X5[q] = cplx{0.0, 0.0};
     }
     __syncthreads();
-    // Left half, one l45 = o at a time.
-    for (int o = 0; o < nd; ++o) {
-      const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
-      if (n4 == 0) continue;  // uniform
-      const int p5 = (lo5 - w5lo) >> 1, p4 = (lo4 - w4lo) >> 1;
-      const double *u2b = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5 + ((lo5 - rp.K_lo2[3]) >> 1)) * nK4 +
-                          ((lo4 - rp.K_lo2[2]) >> 1);
-      // Z5(i1, k4) = p1(i1) sum_k5 U1(i1, k5) u5(k5) U2(k5, k4)
-      for (int q = tid; q < iw * kl; q += AT) {
-        const int i = q / kl, k4i = q % kl;
+    // Left half, the l45 = o values ng at a time.
+    for (int og = 0; og < nd; og += ng) {
+      const int gn = imin(ng, nd - og);
+      // Z5_o(i1, k4) = p1(i1) sum_k5 U1(i1, k5) u5(k5) U2(k5, k4);  Q5_o(k5, i1) = sum_k4 U2(k5, k4)
+      // u4(k4) R4(k4, i1), for every o of the group.
+      for (int q = tid; q < gn * 2 * iw * kl; q += AT) {
+        const int gi = q / (2 * iw * kl), r = q - gi * (2 * iw * kl), o = og + gi;
+        const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
+        const int p5 = (lo5 - w5lo) >> 1, p4 = (lo4 - w4lo) >> 1;
+        const double *u2b = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5 + ((lo5 - rp.K_lo2[3]) >> 1)) * nK4 +
+                            ((lo4 - rp.K_lo2[2]) >> 1);
         cplx v{0.0, 0.0};
-        if (i < d1 && k4i < n4) {
-          for (int k5i = 0; k5i < n5; ++k5i)
-            v = cfma(v, u5[o * kl + k5i], U1s[i * kw + p5 + k5i] * u2b[(int64_t)k5i * nK4 + k4i]);
-          v = cmul(v, P1[i]);
+        if (r < iw * kl) {
+          const int i = r / kl, k4i = r % kl;
+          if (i < d1 && k4i < n4) {
+            for (int k5i = 0; k5i < n5; ++k5i)
+              v = cfma(v, u5[o * kl + k5i], U1s[i * kw + p5 + k5i] * u2b[(int64_t)k5i * nK4 + k4i]);
+            v = cmul(v, P1[i]);
+          }
+          Z5[gi * iw * kl + r] = v;
+        } else {
+          const int r2 = r - iw * kl, k5i = r2 / iw, i = r2 % iw;
+          if (k5i < n5 && i < d1)
+            for (int k4i = 0; k4i < n4; ++k4i)
+              v = cadd(v, cmul(u4[o * kl + k4i], cscale(R4[(p4 + k4i) * iw + i], u2b[(int64_t)k5i * nK4 + k4i])));
+          Q5[gi * kl * iw + r2] = v;
         }
-        Z5[q] = v;
-      }
-      // Q5(k5, i1) = sum_k4 U2(k5, k4) u4(k4) R4(k4, i1)
-      for (int q = tid; q < kl * iw; q += AT) {
-        const int k5i = q / iw, i = q % iw;
-        cplx v{0.0, 0.0};
-        if (k5i < n5 && i < d1)
-          for (int k4i = 0; k4i < n4; ++k4i)
-            v = cadd(v, cmul(u4[o * kl + k4i], cscale(R4[(p4 + k4i) * iw + i], u2b[(int64_t)k5i * nK4 + k4i])));
-        Q5[q] = v;
       }
       __syncthreads();
-      // G4(k4) += sum_i1 Z5(i1, k4) R4(k4, i1);  G5(k5) += sum_i1 p1(i1) U1(i1, k5) Q5(k5, i1);
-      // X5(i1, k4) += Z5(i1, k4) u4(k4)
-      for (int q = tid; q < 2 * kl + iw * kl; q += AT) {
-        if (q < kl) {
-          const int k4i = q;
+      // G4_o(k4) += sum_i1 Z5_o(i1, k4) R4(k4, i1);  G5_o(k5) += sum_i1 p1(i1) U1(i1, k5) Q5_o(k5, i1);
+      // X5(i1, k4) += Z5_o(i1, k4) u4_o(k4), the group's o in increasing order.
+      for (int q = tid; q < gn * 2 * kl + iw * kw; q += AT) {
+        if (q < gn * kl) {
+          const int gi = q / kl, k4i = q - gi * kl, o = og + gi;
+          const int n4 = rng[3 * nd + o], p4 = (rng[2 * nd + o] - w4lo) >> 1;
           if (k4i < n4) {
             cplx v{0.0, 0.0};
-            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(Z5[i * kl + k4i], R4[(p4 + k4i) * iw + i]));
+            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(Z5[(gi * iw + i) * kl + k4i], R4[(p4 + k4i) * iw + i]));
             G4[o * kl + k4i] = cadd(G4[o * kl + k4i], v);
           }
-        } else if (q < 2 * kl) {
-          const int k5i = q - kl;
+        } else if (q < gn * 2 * kl) {
+          const int qq = q - gn * kl, gi = qq / kl, k5i = qq - gi * kl, o = og + gi;
+          const int n5 = rng[1 * nd + o], p5 = (rng[0 * nd + o] - w5lo) >> 1;
           if (k5i < n5) {
             cplx v{0.0, 0.0};
-            for (int i = 0; i < d1; ++i) v = cadd(v, cmul(P1[i], cscale(Q5[k5i * iw + i], U1s[i * kw + p5 + k5i])));
+            for (int i = 0; i < d1; ++i)
+              v = cadd(v, cmul(P1[i], cscale(Q5[(gi * kl + k5i) * iw + i], U1s[i * kw + p5 + k5i])));
             G5[o * kl + k5i] = cadd(G5[o * kl + k5i], v);
           }
         } else {
-          const int r = q - 2 * kl, i = r / kl, k4i = r % kl;
-          if (i < d1 && k4i < n4) X5[i * kw + p4 + k4i] = cadd(X5[i * kw + p4 + k4i], cmul(Z5[r], u4[o * kl + k4i]));
+          const int r = q - gn * 2 * kl, i = r / kw, p = r - i * kw;
+          if (i < d1) {
+            cplx v = X5[r];
+            for (int gi = 0; gi < gn; ++gi) {
+              const int o = og + gi, n4 = rng[3 * nd + o], k4i = p - ((rng[2 * nd + o] - w4lo) >> 1);
+              if (k4i >= 0 && k4i < n4) v = cadd(v, cmul(Z5[(gi * iw + i) * kl + k4i], u4[o * kl + k4i]));
+            }
+            X5[r] = v;
+          }
         }
       }
       __syncthreads();
@@ -323,37 +336,44 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
       R3[q] = v;
     }
     __syncthreads();
-    // Right half, one l23 = o at a time.
-    for (int o = 0; o < nd; ++o) {
-      const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
-      if (n3 == 0) continue;  // uniform
-      const int p3 = (lo3 - w3lo) >> 1, p2 = (lo2 - w2lo) >> 1;
-      const double *u4b = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + ((lo3 - rp.K_lo2[1]) >> 1)) * nK2 +
-                          ((lo2 - rp.K_lo2[0]) >> 1);
-      // G3(k3) += sum_i1 R3(i1, k3) V2(k3, i1);  S2(i1, k2) = sum_k3 R3(i1, k3) u3(k3) U4(k3, k2)
-      for (int q = tid; q < kl + iw * kl; q += AT) {
-        if (q < kl) {
-          const int k3i = q;
+    // Right half, the l23 = o values ng at a time.
+    for (int og = 0; og < nd; og += ng) {
+      const int gn = imin(ng, nd - og);
+      // G3_o(k3) += sum_i1 R3(i1, k3) V2_o(k3, i1);  S2_o(i1, k2) = sum_k3 R3(i1, k3) u3(k3) U4(k3, k2)
+      for (int q = tid; q < gn * (kl + iw * kl); q += AT) {
+        if (q < gn * kl) {
+          const int gi = q / kl, k3i = q - gi * kl, o = og + gi;
+          const int n3 = rng[7 * nd + o], p3 = (rng[6 * nd + o] - w3lo) >> 1;
           if (k3i < n3) {
             cplx v{0.0, 0.0};
             for (int i = 0; i < d1; ++i) v = cadd(v, cmul(R3[i * kw + p3 + k3i], V2[(o * kl + k3i) * iw + i]));
             G3[o * kl + k3i] = cadd(G3[o * kl + k3i], v);
           }
         } else {
-          const int r = q - kl, i = r / kl, k2i = r % kl;
+          const int qq = q - gn * kl, gi = qq / (iw * kl), r = qq - gi * (iw * kl), o = og + gi;
+          const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
+          const int p3 = (lo3 - w3lo) >> 1;
+          const int i = r / kl, k2i = r % kl;
           cplx v{0.0, 0.0};
-          if (i < d1 && k2i < n2)
+          if (i < d1 && k2i < n2) {
+            const double *u4b = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + ((lo3 - rp.K_lo2[1]) >> 1)) * nK2 +
+                                ((lo2 - rp.K_lo2[0]) >> 1);
             for (int k3i = 0; k3i < n3; ++k3i)
               v = cadd(v, cmul(u3[o * kl + k3i], cscale(R3[i * kw + p3 + k3i], u4b[(int64_t)k3i * nK2 + k2i])));
-          S2[r] = v;
+          }
+          S2[gi * iw * kl + r] = v;
         }
       }
       __syncthreads();
-      // G2(k2) += sum_i1 S2(i1, k2) U5(k2, i1)
-      for (int k2i = tid; k2i < n2; k2i += AT) {
-        cplx v{0.0, 0.0};
-        for (int i = 0; i < d1; ++i) v = cfma(v, S2[i * kl + k2i], U5s[(p2 + k2i) * iw + i]);
-        G2[o * kl + k2i] = cadd(G2[o * kl + k2i], v);
+      // G2_o(k2) += sum_i1 S2_o(i1, k2) U5(k2, i1)
+      for (int q = tid; q < gn * kl; q += AT) {
+        const int gi = q / kl, k2i = q - gi * kl, o = og + gi;
+        const int n2 = rng[5 * nd + o], p2 = (rng[4 * nd + o] - w2lo) >> 1;
+        if (k2i < n2) {
+          cplx v{0.0, 0.0};
+          for (int i = 0; i < d1; ++i) v = cfma(v, S2[(gi * iw + i) * kl + k2i], U5s[(p2 + k2i) * iw + i]);
+          G2[o * kl + k2i] = cadd(G2[o * kl + k2i], v);
+        }
       }
       __syncthreads();
     }
@@ -414,7 +434,7 @@ __global__ void adjoint_ring_reduce_kernel(RingParams rp, PsiPtrs psi, const dou
 
 }  // namespace
 
-void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw) {
+void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw, int &ng) {
   const int nd = p.nd, nd3 = nd * nd * nd;
   kl = std::max(1, p.kmax);
   iw = std::max(1, p.i[0].n);
@@ -443,9 +463,15 @@ void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw) {
     for (int q = 0; q < 4; ++q)
       if (hi[q] >= 0) kw = std::max(kw, (hi[q] - lo[q]) / 2 + 1);
   }
+  // Spins per group of the two halves: as many as keep two workgroups on a CU (half the LDS),
+  // or, when even one does not, as many as fit one workgroup.
+  const size_t two = kAdjRingMaxLds / 2 - 1024;
+  const size_t cap = adj_geom(nd, kl, iw, kw, 1).bytes <= two ? two : kAdjRingMaxLds;
+  ng = 1;
+  while (ng < nd && adj_geom(nd, kl, iw, kw, ng + 1).bytes <= cap) ++ng;
 }
 
-size_t adjoint_ring_smem(int nd, int kl, int iw, int kw) { return adj_geom(nd, kl, iw, kw).bytes; }
+size_t adjoint_ring_smem(int nd, int kl, int iw, int kw, int ng) { return adj_geom(nd, kl, iw, kw, ng).bytes; }
 size_t adjoint_ring_gbuf_bytes(int nd, int kl) {
   return sizeof(double) * 2 * (size_t)nd * nd * nd * nd * 4 * nd * kl;
 }
@@ -455,15 +481,15 @@ hipError_t adjoint_ring_init_attributes() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kAdjRingMaxLds);
 }
 
-hipError_t launch_adjoint_ring(const RingParams &rp, int kl, int iw, int kw, const double *const psi[5],
-                               double *gbuf, int64_t total, double gre, double gim, double *grad_b,
-                               hipStream_t s) {
+hipError_t launch_adjoint_ring(const RingParams &rp, int kl, int iw, int kw, int ng,
+                               const double *const psi[5], double *gbuf, int64_t total, double gre,
+                               double gim, double *grad_b, hipStream_t s) {
   PsiPtrs pp;
   for (int a = 0; a < 5; ++a) pp.p[a] = psi[a];
   const int nd = rp.nd;
-  const size_t bytes = adj_geom(nd, kl, iw, kw).bytes;
-  if (nd > kAdjRingMaxNd || bytes > kAdjRingMaxLds) return hipErrorInvalidValue;
-  adjoint_ring_kernel<<<nd * nd * nd * nd, AT, bytes, s>>>(rp, pp, gbuf, kl, iw, kw);
+  const size_t bytes = adj_geom(nd, kl, iw, kw, ng).bytes;
+  if (nd > kAdjRingMaxNd || ng < 1 || bytes > kAdjRingMaxLds) return hipErrorInvalidValue;
+  adjoint_ring_kernel<<<nd * nd * nd * nd, AT, bytes, s>>>(rp, pp, gbuf, kl, iw, kw, ng);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (total <= 0) return hipSuccess;

@@ -1473,10 +1473,10 @@ int eprl_contract_boundary_adjoint(eprl_ctx *c, const int two_j[10], int dl, con
   if (!grad_boosters) return EPRL_OK;
   if (!B) return fail(c, EPRL_EINVAL, "null booster pointer");
   if (probe.kmax > 16) return fail(c, EPRL_ERANGE, "intertwiner dimensions above 16 are not supported");
-  int akl = 0, aiw = 0, akw = 0;
+  int akl = 0, aiw = 0, akw = 0, ang = 1;
   if (c->algo != EPRL_ALGO_SHELL && probe.ring_KW != 0 && probe.nd <= kAdjRingMaxNd)
-    adjoint_ring_dims(probe, akl, aiw, akw);
-  if (akl > 0 && adjoint_ring_smem(probe.nd, akl, aiw, akw) <= kAdjRingMaxLds) {
+    adjoint_ring_dims(probe, akl, aiw, akw, ang);
+  if (akl > 0 && adjoint_ring_smem(probe.nd, akl, aiw, akw, ang) <= kAdjRingMaxLds) {
     // Factorised order: per-core G vectors, then a fixed-order sum per booster entry.
     Prepared prep;
     rc = prepare(c, two_j, dl, align_up(adjoint_ring_gbuf_bytes(probe.nd, akl), 256), prep, true,
@@ -1484,7 +1484,7 @@ int eprl_contract_boundary_adjoint(eprl_ctx *c, const int two_j[10], int dl, con
     if (rc) return rc;
     RingParams rp = ring_params(prep, B);
     TimedLaunch tl(c, 3);
-    HIP_TRY(c, launch_adjoint_ring(rp, akl, aiw, akw, psi, reinterpret_cast<double *>(prep.tail),
+    HIP_TRY(c, launch_adjoint_ring(rp, akl, aiw, akw, ang, psi, reinterpret_cast<double *>(prep.tail),
                                    prep.plan.boff.back(), grad_F[0], grad_F[1], grad_boosters, c->stream));
     return EPRL_OK;
   }

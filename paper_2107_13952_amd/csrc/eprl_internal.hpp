@@ -282,14 +282,15 @@ hipError_t launch_adjoint_shells(const AdjointParams &ap, hipStream_t s);
 constexpr int kAdjRingMaxNd = 11;
 constexpr size_t kAdjRingMaxLds = 160 * 1024 - 256;
 // LDS sizes of the kernel for a configuration: kl = largest k range of a spin, iw = number of i1
-// values, kw = widest core window of k5, k4 (over l45), k3 or k2 (over l23).
-void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw);
-size_t adjoint_ring_smem(int nd, int kl, int iw, int kw);
+// values, kw = widest core window of k5, k4 (over l45), k3 or k2 (over l23), ng = spins per group
+// of the two halves.
+void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw, int &ng);
+size_t adjoint_ring_smem(int nd, int kl, int iw, int kw, int ng);
 size_t adjoint_ring_gbuf_bytes(int nd, int kl);
 hipError_t adjoint_ring_init_attributes();
-hipError_t launch_adjoint_ring(const RingParams &rp, int kl, int iw, int kw, const double *const psi[5],
-                               double *gbuf, int64_t total, double gre, double gim, double *grad_b,
-                               hipStream_t s);
+hipError_t launch_adjoint_ring(const RingParams &rp, int kl, int iw, int kw, int ng,
+                               const double *const psi[5], double *gbuf, int64_t total, double gre,
+                               double gim, double *grad_b, hipStream_t s);
 hipError_t launch_adjoint_reduce(const AdjointParams &ap, int64_t total, double gre, double gim,
                                  double *grad_b, hipStream_t s);
 
