@@ -197,6 +197,8 @@ def plain_j3(lib, torch, dev, synthetic, autotune, steps):
     terms = lib.count_terms(two_j, dl)[1]
     work = lib.count_work(two_j, dl)
     tuned = lib.autotune(two_j, dl, b, out) if autotune else None
+    # (target workgroups, staging level) of the work split the timed calls use
+    split = (tuned["target_workgroups"], tuned["staging_level"]) if tuned else (8192, 2)
     ms = event_times(torch, lambda: lib.vertex_tensor(two_j, dl, 1.2, b, out=out), steps, 3)
     lib.timing_enable(True)
     for _ in range(steps):
@@ -215,7 +217,8 @@ def plain_j3(lib, torch, dev, synthetic, autotune, steps):
                             "frac": work["ring_useful_flops"] / (ring_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                             "mfma_executed_tflops": work["ring_mfma_flops"] / (ring_ms * 1e-3) / 1e12,
                             "traffic": measured_traffic("ring_kernel_j3_dl8_counters.md",
-                                                        "traffic bytes per launch, split 8192 2", "ring.hip")}}
+                                                        "traffic bytes per launch, split "
+                                                        f"{split[0]} {split[1]}", "ring.hip")}}
 
 
 def irregular_batch(lib, torch, dev, reps):
@@ -319,8 +322,9 @@ def differentiation(lib, torch, dev):
 
 
 def counter_workload(lib, torch, dev, which):
-    """The kernel named by `which` three times, then a plain 256 MiB device copy three times (the
-    copy calibrates what FETCH_SIZE and WRITE_SIZE read for a known number of bytes)."""
+    """The kernel named by `which` three times (the large-spin batch, the j = 3, dl = 8 vertex, or
+    that vertex in the per-shell order), then a plain 256 MiB device copy three times (the copy
+    calibrates what FETCH_SIZE and WRITE_SIZE read for a known number of bytes)."""
     if which == "batch":
         lb = LargeBatch(lib, torch, dev)
         for _ in range(3):
@@ -330,8 +334,11 @@ def counter_workload(lib, torch, dev, which):
         two_j, dl = cfg["two_j"], cfg["dl"]
         b = torch.from_numpy(workloads.synthetic_boosters(cfg["booster_seed"],
                                                           block_shapes(lib, two_j, dl))).to(dev)
+        # "j3shell": the per-shell order of the framed algorithm on the same vertex.
+        lib.set_algorithm("shell" if which == "j3shell" else "auto")
         for _ in range(3):
             lib.vertex_tensor(two_j, dl, 1.2, b)
+        lib.set_algorithm("auto")
     torch.cuda.synchronize()
     x = torch.ones(32 << 20, dtype=torch.float64, device=dev)
     y = torch.empty_like(x)
@@ -353,7 +360,7 @@ def main():
     ap.add_argument("--synthetic-boosters", action="store_true",
                     help="seeded boosters for the j=3 block instead of the stored quadrature ones")
     ap.add_argument("--no-autotune", action="store_true", help="default work split for the j=3 block")
-    ap.add_argument("--counter-workload", choices=["batch", "j3"],
+    ap.add_argument("--counter-workload", choices=["batch", "j3", "j3shell"],
                     help="run one kernel three times and a calibration copy for rocprofv3 --pmc, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
