@@ -228,14 +228,23 @@ def irregular_batch(lib, torch, dev, reps):
         workloads.batch_booster_seed(workloads.CFG3_SEED, c), block_shapes(lib, tj, d))).to(dev)
         for c, (tj, d) in enumerate(configs)]
     terms = sum(lib.count_terms(tj, d)[1] for tj, d in configs)
-    outs = lib.vertex_tensor_batched(configs, 1.2, bl)
+    outs = [torch.empty(lib.layout(tj, d)[0], dtype=torch.float64, device=dev) for tj, d in configs]
+    # First call of a new batch shape: planning, schedules, metadata upload, graph capture and
+    # the run itself (host wall clock).
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lib.vertex_tensor_batched(configs, 1.2, bl, outs)
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
     tb = event_times(torch, lambda: lib.vertex_tensor_batched(configs, 1.2, bl, outs), reps)
     tp = event_times(torch, lambda: [lib.vertex_tensor(tj, d, 1.2, bb, out=a)
                                      for (tj, d), bb, a in zip(configs, bl, outs)], reps)
     return {"workload": "64 seeded configurations, j in 1/2..6, dl in 3..10", "terms": terms,
             "batched_terms_per_s": terms / (statistics.median(tb) * 1e-3),
             "plain_terms_per_s": terms / (statistics.median(tp) * 1e-3),
-            "batched": spread(tb), "plain": spread(tp)}
+            "batched": spread(tb), "plain": spread(tp),
+            "first_call_ms": first_ms,
+            "first_call_host_ms_estimate": first_ms - statistics.median(tb)}
 
 
 def shell_scan(lib, torch, dev, reps):
