@@ -244,7 +244,7 @@ int eprl_contract_trailing(eprl_ctx *ctx, const int dims_i[5], const double *A, 
  *   F = (-1)^x (2x + 1) sum_{k1, k2, k3} (-1)^(k1 + k2 + k3) TA[k1][k2] TB[k3][k1] TC[k2][k3]
  * (each matrix is the eprl_contract_trailing output of one vertex, m = 3, row-major over its
  * first two intertwiners; the triangle runs k1 -> k2 -> k3 -> k1).  TA, TB, TC: device complex
- * n x n; F: device complex.  EPRL_EINVAL unless 1 <= n <= 1024 and two_klo, two_x are even
+ * n x n; F: device complex.  EPRL_EINVAL unless 1 <= n <= 256 and two_klo, two_x are even
  * (integer spins: the phases are then real). */
 int eprl_contract_delta3(eprl_ctx *ctx, int n, int two_klo, int two_x, const double *TA,
                          const double *TB, const double *TC, double *F);

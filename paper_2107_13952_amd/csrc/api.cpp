@@ -1415,7 +1415,7 @@ int eprl_contract_delta3(eprl_ctx *c, int n, int two_klo, int two_x, const doubl
                          const double *TB, const double *TC, double *F) {
   if (check_ctx(c)) return EPRL_EINVAL;
   if (!TA || !TB || !TC || !F) return fail(c, EPRL_EINVAL, "null argument");
-  if (n < 1 || n > 1024) return fail(c, EPRL_EINVAL, "bulk intertwiner range must hold 1..1024 values");
+  if (n < 1 || n > 256) return fail(c, EPRL_EINVAL, "bulk intertwiner range must hold 1..256 values");
   if (two_klo < 0 || two_x < 0 || (two_klo & 1) || (two_x & 1))
     return fail(c, EPRL_EINVAL, "bulk intertwiners and the internal spin must be integer spins");
   HIP_TRY(c, launch_delta3(n, two_klo, two_x, TA, TB, TC, F, c->stream));

@@ -77,7 +77,7 @@ def test_contract_trailing(lib, torch, shape, m):
 
 def test_contract_delta3_random(lib, torch):
     rng = np.random.default_rng(7)
-    for n, two_klo, two_x in [(1, 0, 0), (5, 2, 4), (33, 0, 8), (64, 4, 2)]:
+    for n, two_klo, two_x in [(1, 0, 0), (5, 2, 4), (33, 0, 8), (64, 4, 2), (128, 0, 2)]:
         ts = [rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)) for _ in range(3)]
         note(f"delta3 n={n} two_klo={two_klo} two_x={two_x}")
         f = complex(lib.contract_delta3(*[torch.from_numpy(t).cuda() for t in ts], two_klo, two_x))
@@ -85,6 +85,10 @@ def test_contract_delta3_random(lib, torch):
         bound = 1e-13 * (two_x + 1) * float(np.einsum("ab,ca,bc->", *[np.abs(t) for t in ts]))
         assert abs(f - ref) <= bound
     eye = torch.eye(3, dtype=torch.complex128, device="cuda")
+    big = torch.zeros((257, 257), dtype=torch.complex128, device="cuda")
+    with pytest.raises(lib.EprlError) as exc:
+        lib.contract_delta3(big, big, big, 0, 0)
+    assert exc.value.code == -1
     for two_klo, two_x in [(1, 0), (0, 3)]:
         with pytest.raises(lib.EprlError) as exc:
             lib.contract_delta3(eye, eye, eye, two_klo, two_x)

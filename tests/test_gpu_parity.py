@@ -319,7 +319,8 @@ def sub_boosters(two_j, dl_max, dl, b):
 
 
 @pytest.mark.parametrize("two_j,dl_max,seed", [([2] * 10, 3, 24),
-                                               ([13, 10, 11, 12, 10, 14, 11, 13, 13, 10], 1, 25)])
+                                               ([13, 10, 11, 12, 10, 14, 11, 13, 13, 10], 1, 25),
+                                               ([4, 1, 1, 4, 4, 3, 3, 1, 4, 1], 0, 26)])
 def test_shell_scan(lib, torch, two_j, dl_max, seed):
     """A(dl) for dl = 0..dl_max from one buffer packed for dl_max: each against the oracle at
     that dl and bitwise against the plain call on its own packed boosters."""
