@@ -31,7 +31,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int WT = 512;          // threads per workgroup
 constexpr int WW = WT / 64;      // wavefronts per workgroup
-constexpr int kMaxAcc = 12;      // accumulator tiles per wavefront
+constexpr int kMaxAcc = 14;      // accumulator tiles per wavefront
 constexpr size_t kLdsBytes = 160 * 1024;
 
 __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
@@ -443,8 +443,9 @@ __global__ __launch_bounds__(WT, 1) void wide_kernel(RingParams rp, int *next) {
 // every item writes its own partial slice, so which workgroup runs it does not matter.  The loop
 // ends for every workgroup once all eight counters have passed the ends of their lists.
 template <bool STG>
-__global__ __launch_bounds__(WT, 1) void wide_batch_kernel(const RingParams *cfgs, const int *items,
-                                                          const int *xoff, int *next) {
+__global__ __launch_bounds__(WT, 1) void wide_batch_kernel(const RingParams *__restrict__ cfgs,
+                                                          const int *__restrict__ items,
+                                                          const int *__restrict__ xoff, int *next) {
   extern __shared__ double smem[];
   __shared__ int it_s;
   const int home = xcc_id();
