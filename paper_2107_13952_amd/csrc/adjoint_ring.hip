@@ -234,6 +234,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
         const double *u4r = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g) * nK2 +
                             ((lo2 - rp.K_lo2[0]) >> 1);
         const int p2 = (lo2 - w2lo) >> 1;
+#pragma unroll 4
         for (int k2i = 0; k2i < n2; ++k2i)
           v = cfma(v, u2[o * kl + k2i], u4r[k2i] * U5s[(p2 + k2i) * iw + i]);
       }
@@ -279,6 +280,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
         if (r < iw * kl) {
           const int i = r / kl, k4i = r % kl;
           if (i < d1 && k4i < n4) {
+#pragma unroll 4
             for (int k5i = 0; k5i < n5; ++k5i)
               v = cfma(v, u5[o * kl + k5i], U1s[i * kw + p5 + k5i] * u2b[(int64_t)k5i * nK4 + k4i]);
             v = cmul(v, P1[i]);
@@ -287,6 +289,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
         } else {
           const int r2 = r - iw * kl, k5i = r2 / iw, i = r2 % iw;
           if (k5i < n5 && i < d1)
+#pragma unroll 4
             for (int k4i = 0; k4i < n4; ++k4i)
               v = cadd(v, cmul(u4[o * kl + k4i], cscale(R4[(p4 + k4i) * iw + i], u2b[(int64_t)k5i * nK4 + k4i])));
           Q5[gi * kl * iw + r2] = v;
@@ -358,6 +361,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
           if (i < d1 && k2i < n2) {
             const double *u4b = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + ((lo3 - rp.K_lo2[1]) >> 1)) * nK2 +
                                 ((lo2 - rp.K_lo2[0]) >> 1);
+#pragma unroll 4
             for (int k3i = 0; k3i < n3; ++k3i)
               v = cadd(v, cmul(u3[o * kl + k3i], cscale(R3[i * kw + p3 + k3i], u4b[(int64_t)k3i * nK2 + k2i])));
           }
