@@ -287,10 +287,21 @@ def booster_builder(lib, torch, dev, reps):
     err = None
     if ref is not None:
         err = float(np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max())
+    # The boosters of configuration 0 of the large-spin batch (spins 5..7, dl = 6): timing and the
+    # quadrature's own error estimate (the oracle would take hours for this one).
+    tj5, d5 = workloads.cfg5_batch()[0]
+    _, _, offs5 = lib.layout(tj5, d5)
+    out5 = torch.empty(int(offs5[-1]), dtype=torch.float64, device=dev)
+    _, info5 = lib.boosters(tj5, d5, 1.2, out=out5)
+    ms5 = event_times(torch, lambda: lib.boosters(tj5, d5, 1.2, out=out5), 2)
     return {"workload": "boosters of the equilateral j=3 (two_j=6), dl=8 vertex, gamma=1.2, "
                         f"{int(offs[-1])} values", "time": spread(ms), "subintervals": info["n"],
             "error_estimate": info["error"], "max_imag": info["imag"],
-            "normwise_vs_oracle_quadrature": err}
+            "normwise_vs_oracle_quadrature": err,
+            "large_spin_config0": {"two_j": list(tj5), "dl": d5, "values": int(offs5[-1]),
+                                   "time": spread(ms5), "subintervals": info5["n"],
+                                   "error_estimate_rel": info5["error"] / float(out5.abs().max()),
+                                   "max_imag": info5["imag"]}}
 
 
 def differentiation(lib, torch, dev):
