@@ -17,10 +17,12 @@
 // operand B[g][c], result register r = D[g + 4 r][c].
 //
 // One workgroup of 8 wavefronts owns a block of rows of A(i1; rho, sig) (all rows when the
-// slice's tiles fit in 12 accumulator tiles per wavefront, else the rows split into row blocks)
+// slice's tiles fit in 14 accumulator tiles per wavefront, else the rows split into row blocks)
 // for a chunk of cores, and keeps it in MFMA accumulators.  LDS holds the T5/T2 tiles, G (then
-// P, in place) for the block's rows and H; booster entries and 6j values are read from global
-// memory (L1/L2) straight into the MFMA operands.  Stages are separated by workgroup barriers.
+// P, in place) for the block's rows, H, the U3 slice of the current x and, when they fit, the
+// core's weighted booster blocks; the other 6j values (and booster entries otherwise) are read
+// from global memory (L1/L2) straight into the MFMA operands.  Stages are separated by workgroup
+// barriers.
 #include "eprl_internal.hpp"
 
 namespace eprl {
@@ -45,8 +47,12 @@ __device__ __forceinline__ d4v mfma(double a, double b, d4v c) {
 // LDS geometry of one configuration (all sizes in doubles).
 struct WideGeom {
   int R, C, RT, CT, RTb, GS, HS;
-  int t5, t2, g, h, mb, meta;  // offsets
+  int t5, t2, g, h, u3, mb, meta;  // offsets
 };
+
+// Row stride of the U3 slice in LDS (rows: k4 positions, columns: k3 positions 0..31; the two
+// halves of a row read by one matrix-core operand fall on opposite halves of the banks).
+constexpr int kU3S = 48;
 
 // stg: the core's four weighted booster blocks are staged in LDS (16 x 16 each per spin value,
 // zero outside the block) for the operands of T5 / T2 and G / H.
@@ -63,7 +69,8 @@ __host__ __device__ inline WideGeom wide_geom(int nd, const int *i_n, int kw, in
   w.t2 = w.t5 + nd * 256;
   w.g = w.t2 + nd * 256;
   w.h = w.g + w.RTb * 16 * w.GS;
-  w.mb = w.h + kw * w.HS;
+  w.u3 = w.h + kw * w.HS;
+  w.mb = w.u3 + kw * kU3S;
   w.meta = w.mb + (stg ? 4 * nd * 256 : 0);
   return w;
 }
@@ -93,6 +100,7 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
   double *T2s = smem + geo.t2;    // [l23][i2][k3 - lo3(l23)]
   double *Gs = smem + geo.g;      // [rho - rho0][k4 position], then P: [rho - rho0][k3 position]
   double *Hs = smem + geo.h;      // [k3 position][sig]
+  double *U3s = smem + geo.u3;    // [k4 position][k3 position]: U3 at x inside the active windows, else 0
   double *Mb = smem + geo.mb;     // [slot: M5, M4, M2, M3][spin value][i][k - lo], when STG
   int *rng = reinterpret_cast<int *>(smem + geo.meta);             // [8][nd]
   int64_t *bo = reinterpret_cast<int64_t *>(rng + 8 * nd);         // [4][nd]
@@ -101,7 +109,7 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
   const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4,
             c = l & 15;
   const int ntw = (ntile - w + WW - 1) / WW;  // accumulator tiles held by this wavefront
-  const int rt0w = w / CT, ct0w = w - rt0w * CT;  // its first tile
+  const int ctm = (2048 + CT - 1) / CT;          // t / CT = (t * ctm) >> 11 for t < 128
   const int *J = rp.two_j;
   const int two_i1 = rp.i_lo2[0] + 2 * n1;
   const int NX = rp.NX, nK2 = rp.K_n[0], nK3 = rp.K_n[1], nK4 = rp.K_n[2], nK5 = rp.K_n[3];
@@ -156,7 +164,7 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
         if (i < di && k < n) v = B[bo[slot * nd + o] + (int64_t)i * n + k] * (double)(lo + 2 * k + 1);
         Mb[q] = v;
       }
-      // (read after the x loop's first barrier)
+      __syncthreads();
     }
     // Core windows of k4 (over l45) and of k3 (over l23).
     int w4lo = 1 << 30, w4hi = -1, w3lo = 1 << 30, w3hi = -1;
@@ -186,7 +194,26 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
       const int a4l = (a4 - w4lo) / 2, b4l = (b4 - w4lo) / 2;
       const int a3l = (a3 - w3lo) / 2, b3l = (b3 - w3lo) / 2;
       const int xg = (x - rp.X_lo2) / 2;
-      __syncthreads();  // previous x's readers of T5s / T2s / Gs / Hs are done
+      // No barrier here: the T stage writes only T5s / T2s (last read in the previous x's G / H
+      // stage) and U3s (last read in its P stage), which barriers already separate; a wavefront
+      // that finishes the previous x's A update early starts the T stage's global reads while
+      // the others are still multiplying.  The barrier after the T stage keeps the G / H writes
+      // behind every wavefront's A update.
+
+      // The U3 slice at x (zero outside the active k4 and k3 windows) is read from global memory
+      // here and written to LDS after the T stage, for the P stage.
+      constexpr int NU3 = 32 * 32 / WT;
+      double u3v[NU3];
+      {
+        const double *u3row = rp.U3 + (u3base + xg) * nK4 * nK3 + ((w3lo - rp.K_lo2[1]) >> 1);
+        const int k4g0 = (w4lo - rp.K_lo2[2]) >> 1;
+#pragma unroll
+        for (int q = 0; q < NU3; ++q) {
+          const int idx = tid + q * WT, kp = idx >> 5, k3l = idx & 31;
+          u3v[q] = 0.0;
+          if (kp >= a4l && kp <= b4l && k3l >= a3l && k3l <= b3l) u3v[q] = u3row[(int64_t)(k4g0 + kp) * nK3 + k3l];
+        }
+      }
 
       // ---- T5 (per l45) and T2 (per l23): 16x16 tiles, K over the k5 (k2) values active at x.
       // A operand: the booster block M5 (M2) of that spin, row c; B operand: the product of the
@@ -241,6 +268,11 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
 #pragma unroll
         for (int r = 0; r < 4; ++r) Ts[(o * 16 + g + 4 * r) * 16 + c] = t[r];
       }
+#pragma unroll
+      for (int q = 0; q < NU3; ++q) {
+        const int idx = tid + q * WT, kp = idx >> 5;
+        if (kp < KW) U3s[kp * kU3S + (idx & 31)] = u3v[q];
+      }
       __syncthreads();
 
       // ---- G (per k4 position) and H (per k3 position): 16x16 tiles, K over l45 (l23), whose
@@ -268,16 +300,20 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
           lok[s] = rng[rlo * nd + oc[s]];
           nk[s] = rng[(rlo + 1) * nd + oc[s]];
         }
+        // Two positions at a time: the operand reads of both are in flight together and their
+        // two chains of multiply-adds interleave.
 #pragma unroll
-        for (int pi = 0; pi < 4; ++pi) {
-          const int p = p0 + pi, kv = wlo + 2 * p;
-          d4v t = d4v{0.0, 0.0, 0.0, 0.0};
-          if (p >= pa && p <= pb) {  // uniform
-            double av[GS3], bv[GS3];
+        for (int pp = 0; pp < 2; ++pp) {
+          double av[2][GS3], bv[2][GS3];
+          bool act[2];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int p = p0 + 2 * pp + q, kv = wlo + 2 * p;
+            act[q] = p >= pa && p <= pb;  // uniform
 #pragma unroll
             for (int s = 0; s < GS3; ++s) {
               const int ki = (kv - lok[s]) >> 1;
-              const bool ok = ov[s] && nk[s] > 0 && kv >= lok[s] && ki < nk[s];
+              const bool ok = act[q] && ov[s] && nk[s] > 0 && kv >= lok[s] && ki < nk[s];
               const int kc = ok ? ki : 0;
               const double tv = Ts[(oc[s] * 16 + c) * 16 + kc];
               // An empty block's offset may be the end of the booster buffer: read its start then.
@@ -285,25 +321,34 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
               const double mv = STG ? Mb[(mslot * nd + oc[s]) * 256 + cm * 16 + kc] : *mp * (double)(kv + 1);
               // G: A = T5 (rows i5), B = M4 (columns i4); H: A = M3 (rows i3), B = T2 (columns i2).
               const double x1 = ok ? tv : 0.0, x2 = (ok && cin) ? mv : 0.0;
-              av[s] = sg ? x1 : x2;
-              bv[s] = sg ? x2 : x1;
+              av[q][s] = sg ? x1 : x2;
+              bv[q][s] = sg ? x2 : x1;
             }
-#pragma unroll
-            for (int s = 0; s < GS3; ++s)
-              if (4 * s < nd) t = mfma(av[s], bv[s], t);
           }
-          if (sg) {
-            // rows i5 = g + 4r, column i4 = c  ->  rho = i5 d4 + i4
+          d4v t[2] = {d4v{0.0, 0.0, 0.0, 0.0}, d4v{0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int rho = (g + 4 * r) * d4 + c - rho0;
-              if (g + 4 * r < d5 && c < d4 && rho >= 0 && rho < nrow) Gs[rho * GS + p] = t[r];
+          for (int s = 0; s < GS3; ++s) {
+            if (4 * s >= nd) break;  // uniform
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+              if (act[q]) t[q] = mfma(av[q][s], bv[q][s], t[q]);
+          }
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int p = p0 + 2 * pp + q;
+            if (sg) {
+              // rows i5 = g + 4r, column i4 = c  ->  rho = i5 d4 + i4
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int rho = (g + 4 * r) * d4 + c - rho0;
+                if (g + 4 * r < d5 && c < d4 && rho >= 0 && rho < nrow) Gs[rho * GS + p] = t[q][r];
+              }
+            } else {
+              // rows i3 = g + 4r, column i2 = c  ->  sig = i3 d2 + i2
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                if (g + 4 * r < d3 && c < d2) Hs[p * HS + (g + 4 * r) * d2 + c] = t[q][r];
             }
-          } else {
-            // rows i3 = g + 4r, column i2 = c  ->  sig = i3 d2 + i2
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (g + 4 * r < d3 && c < d2) Hs[p * HS + (g + 4 * r) * d2 + c] = t[r];
           }
         }
       }
@@ -311,25 +356,19 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
 
       // ---- P = G U3 for the block's rows, written over G row tile by row tile (a wavefront
       // reads and writes only its own row tiles, and finishes reading before it writes).  The
-      // operands of four k4 steps are loaded before their multiply-adds.
+      // operands of four k4 steps are loaded (from LDS) before their multiply-adds.
       const int nq = ((b3l | 3) + 16) / 16;  // k3 column tiles (1 or 2)
-      const double *u3row = rp.U3 + (u3base + xg) * nK4 * nK3 + ((w3lo - rp.K_lo2[1]) >> 1);
-      const int k4g0 = (w4lo - rp.K_lo2[2]) >> 1;
       for (int rt = w; rt < rtn; rt += WW) {
         d4v pq0 = d4v{0.0, 0.0, 0.0, 0.0}, pq1 = d4v{0.0, 0.0, 0.0, 0.0};
         for (int ks = g0; ks <= b4l; ks += 16) {
           double av[4], b0[4], b1[4];
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
-            const int kp = ks + 4 * s + g;
-            const bool kin = kp >= a4l && kp <= b4l;
-            const int kpc = kin ? kp : a4l;
-            av[s] = Gs[(rt * 16 + c) * GS + (kp < KW ? kp : KW - 1)];
-            const double *u3 = u3row + (int64_t)(k4g0 + kpc) * nK3;
-            const bool q0 = kin && c >= a3l && c <= b3l, q1 = kin && 16 + c >= a3l && 16 + c <= b3l;
-            const double v0 = u3[q0 ? c : a3l], v1 = u3[q1 ? 16 + c : a3l];
-            b0[s] = q0 ? v0 : 0.0;
-            b1[s] = q1 ? v1 : 0.0;
+            // Positions past the window's last multiple of four are never multiplied: clamp.
+            const int kp = ks + 4 * s + g, kr = kp < KW ? kp : KW - 1;
+            av[s] = Gs[(rt * 16 + c) * GS + kr];
+            b0[s] = U3s[kr * kU3S + c];
+            b1[s] = U3s[kr * kU3S + 16 + c];
           }
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
@@ -349,26 +388,21 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
       __syncthreads();
 
       // ---- A(i1; rho, sig) += P H over the active k3 positions.  This wavefront's tiles are
-      // t = w + 8 j, j < ntw, walked in order from (rt0, ct0) without divisions; per k step the
-      // operands of half of them are read from LDS before their multiply-adds.
+      // t = w + 8 j, j < ntw (row tile t / CT by a multiply-shift, exact for t < 128 and
+      // CT <= 16); per k step the operands of half of them are read from LDS, all reads in flight
+      // together (a tile past the end reads tile 0's operands and skips its multiply-add), before
+      // their multiply-adds.
       const double *pa = Gs + c * GS + g, *pb = Hs + g * HS + c;  // this lane's parts of both operands
       for (int ks = h0; ks <= b3l; ks += 4) {
-        int rt = rt0w, ct = ct0w;
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
           double av[kMaxAcc / 2], bv[kMaxAcc / 2];
 #pragma unroll
           for (int jj = 0; jj < kMaxAcc / 2; ++jj) {
-            const int j = half * (kMaxAcc / 2) + jj;
-            if (j < ntw) {
-              av[jj] = pa[rt * 16 * GS + ks];
-              bv[jj] = pb[ks * HS + ct * 16];
-              ct += WW;
-              while (ct >= CT) {
-                ct -= CT;
-                ++rt;
-              }
-            }
+            const int j = half * (kMaxAcc / 2) + jj, t = w + WW * j, tc = t < ntile ? t : 0;
+            const int rt = (tc * ctm) >> 11, ct = tc - rt * CT;
+            av[jj] = pa[rt * 16 * GS + ks];
+            bv[jj] = pb[ks * HS + ct * 16];
           }
 #pragma unroll
           for (int jj = 0; jj < kMaxAcc / 2; ++jj) {
