@@ -354,6 +354,23 @@ int triad_count(int lo, int n, int a, int x) {
 
 }  // namespace
 
+// Accumulator tiles the wide kernel's A update multiplies per k step, summed over the row
+// blocks and the eight wavefronts of a workgroup: wavefront w holds the tiles w + 8 j of its
+// block and runs them in groups of three (the last group of the fourteen holds two), a group
+// whole once it holds one of them.
+static int wide_update_tiles(int RT, int CT, int nrb) {
+  const int RTb = (RT + nrb - 1) / nrb;
+  int total = 0;
+  for (int rb = 0; rb < nrb; ++rb) {
+    const int ntile = std::max(0, std::min(RTb, RT - rb * RTb)) * CT;
+    for (int w = 0; w < 8; ++w) {
+      const int ntw = std::max(0, (ntile - w + 7) / 8);
+      total += std::min(14, (ntw + 2) / 3 * 3);
+    }
+  }
+  return total;
+}
+
 void count_work(const Plan &p, double out[5]) {
   const int nd = p.nd, nd3 = nd * nd * nd;
   const int *J = p.two_j;
@@ -471,8 +488,9 @@ void count_work(const Plan &p, double out[5]) {
                 }
                 const int RT = (d5 * d4 + 15) / 16, CT = (d3 * d2 + 15) / 16;
                 const int nq = ((((b3 - w3lo) / 2) | 3) + 16) / 16;
+                const int upd_tiles = wide_update_tiles(RT, CT, p.ring_nrb);
                 const double per_block = tsteps + (double)(na4 + na3) * ((nd + 3) / 4);
-                executed += 2048.0 * (p.ring_nrb * per_block + (double)RT * nq * s4 + (double)RT * CT * s3);
+                executed += 2048.0 * (p.ring_nrb * per_block + (double)RT * nq * s4 + (double)upd_tiles * s3);
               } else {
                 executed += 2.0 * rows * KW * 4 * s4 + 2.0 * rows * cols * 4 * s3;
               }

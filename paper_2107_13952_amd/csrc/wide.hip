@@ -34,6 +34,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 constexpr int WT = 512;          // threads per workgroup
 constexpr int WW = WT / 64;      // wavefronts per workgroup
 constexpr int kMaxAcc = 14;      // accumulator tiles per wavefront
+constexpr int kAccGroup = 3;     // accumulator tiles per branch of the A update
 constexpr size_t kLdsBytes = 160 * 1024;
 
 __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
@@ -389,25 +390,29 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
 
       // ---- A(i1; rho, sig) += P H over the active k3 positions.  This wavefront's tiles are
       // t = w + 8 j, j < ntw (row tile t / CT by a multiply-shift, exact for t < 128 and
-      // CT <= 16); per k step the operands of half of them are read from LDS, all reads in flight
-      // together (a tile past the end reads tile 0's operands and skips its multiply-add), before
-      // their multiply-adds.
+      // CT <= 16), taken in groups of kAccGroup: a group is skipped when it holds no tile of the
+      // wavefront, else all of its multiply-adds run (a tile past the end reads tile 0's operands
+      // into an accumulator that is never written out), with no branch per tile; the operands of
+      // a group are read from LDS, all reads in flight together, before its multiply-adds.
       const double *pa = Gs + c * GS + g, *pb = Hs + g * HS + c;  // this lane's parts of both operands
       for (int ks = h0; ks <= b3l; ks += 4) {
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          double av[kMaxAcc / 2], bv[kMaxAcc / 2];
+        for (int j0 = 0; j0 < kMaxAcc; j0 += kAccGroup) {
+          if (j0 < ntw) {  // uniform
+            double av[kAccGroup], bv[kAccGroup];
 #pragma unroll
-          for (int jj = 0; jj < kMaxAcc / 2; ++jj) {
-            const int j = half * (kMaxAcc / 2) + jj, t = w + WW * j, tc = t < ntile ? t : 0;
-            const int rt = (tc * ctm) >> 11, ct = tc - rt * CT;
-            av[jj] = pa[rt * 16 * GS + ks];
-            bv[jj] = pb[ks * HS + ct * 16];
-          }
+            for (int jj = 0; jj < kAccGroup; ++jj) {
+              if (j0 + jj >= kMaxAcc) break;
+              const int t = w + WW * (j0 + jj), tc = t < ntile ? t : 0;
+              const int rt = (tc * ctm) >> 11, ct = tc - rt * CT;
+              av[jj] = pa[rt * 16 * GS + ks];
+              bv[jj] = pb[ks * HS + ct * 16];
+            }
 #pragma unroll
-          for (int jj = 0; jj < kMaxAcc / 2; ++jj) {
-            const int j = half * (kMaxAcc / 2) + jj;
-            if (j < ntw) acc[j] = mfma(av[jj], bv[jj], acc[j]);
+            for (int jj = 0; jj < kAccGroup; ++jj) {
+              if (j0 + jj >= kMaxAcc) break;
+              acc[j0 + jj] = mfma(av[jj], bv[jj], acc[j0 + jj]);
+            }
           }
         }
       }
