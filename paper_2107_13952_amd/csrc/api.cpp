@@ -18,6 +18,7 @@ struct BatchEntry {
   Plan plan;
   bool ring = false;
   size_t tables = 0, boff = 0, kr = 0, sched = 0, partial = 0;  // byte offsets in the workspace
+  int towner = -1;              // configuration whose 6j tables this one reads (itself: builds them)
   int nchunk = 0;
   int64_t chunk = 0;
   std::vector<int> bounds;      // chunk bounds of the factorised path
@@ -112,6 +113,22 @@ struct eprl_ctx {
 };
 
 namespace {
+
+// Whether the ring tables of plan r hold every entry the factorised kernels read for plan q: the
+// same spins, at least as many spin offsets, and virtual-spin and x ranges that contain q's.
+bool tables_contain(const Plan &r, const Plan &q) {
+  if (r.nd < q.nd) return false;
+  for (int t = 0; t < 10; ++t)
+    if (r.two_j[t] != q.two_j[t]) return false;
+  if (r.i[0].lo2 != q.i[0].lo2 || r.i[0].n != q.i[0].n) return false;
+  auto inside = [](int rlo, int rn, int qlo, int qn) {
+    if (qn <= 0) return true;
+    return rn > 0 && ((qlo - rlo) & 1) == 0 && rlo <= qlo && rlo + 2 * (rn - 1) >= qlo + 2 * (qn - 1);
+  };
+  for (int e = 0; e < 4; ++e)
+    if (!inside(r.K[e].lo2, r.K[e].n, q.K[e].lo2, q.K[e].n)) return false;
+  return inside(r.X.lo2, r.X.n, q.X.lo2, q.X.n);
+}
 
 int fail(eprl_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
@@ -411,6 +428,9 @@ RingParams ring_params(const Prepared &prep, const double *B) {
   }
   rp.X_lo2 = p.X.lo2;
   rp.NX = p.X.n;
+  rp.tnd = p.nd;
+  rp.xlo2 = p.X.lo2;
+  rp.xhi2 = p.X.lo2 + 2 * (p.X.n - 1);
   rp.U1 = prep.tables + p.toff[0];
   rp.U2 = prep.tables + p.toff[1];
   rp.U3 = prep.tables + p.toff[2];
@@ -680,6 +700,7 @@ hipError_t enqueue_batch(eprl_ctx *c) {
   hipError_t e = hipSuccess;
   for (int q = 0; q < n && e == hipSuccess; ++q) {
     const BatchEntry &b = seq.ent[q];
+    if (b.towner != q) continue;  // reads another configuration's tables
     TableParams tp = table_params(b.plan, reinterpret_cast<double *>(ws + b.tables), c);
     TimedLaunch tl(c, 0);
     e = b.ring ? launch_ring_tables(tp, b.plan.toff[5], c->stream)
@@ -844,8 +865,6 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     batch_chunks(p, b.ring, p.ring_cls >= 0 ? c->tune_wg[p.ring_cls] : 0, b.nchunk, b.chunk,
                  b.bounds, b.ccost);
     fact_max = std::max(fact_max, p.fact_max);
-    b.tables = off;
-    off += align_up((size_t)p.toff[5] * sizeof(double), 256);
     b.boff = off;
     off += align_up(p.boff.size() * sizeof(int64_t), 256);
     b.kr = off;
@@ -855,6 +874,29 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
     b.partial = off;
     off += align_up((size_t)b.nchunk * p.a_size * sizeof(double), 256);
   }
+  // 6j tables: a factorised configuration whose table index ranges (virtual spins, x, spin
+  // offsets) lie inside those of another of the same spins reads that one's tables, the one with
+  // the most spin offsets (the levels of a shell scan share the tables of the largest dl); the
+  // others build their own.
+  for (int q = 0; q < n; ++q) {
+    ent[q].towner = q;
+    if (!ent[q].ring) continue;
+    for (int r = 0; r < n; ++r)
+      if (r != q && ent[r].ring && ent[r].plan.nd > ent[ent[q].towner].plan.nd &&
+          tables_contain(ent[r].plan, ent[q].plan))
+        ent[q].towner = r;
+  }
+  for (int q = 0; q < n; ++q) {  // containment is transitive: follow to a builder
+    int t = ent[q].towner;
+    while (ent[t].towner != t) t = ent[t].towner;
+    ent[q].towner = t;
+  }
+  for (int q = 0; q < n; ++q)
+    if (ent[q].towner == q) {
+      ent[q].tables = off;
+      off += align_up((size_t)ent[q].plan.toff[5] * sizeof(double), 256);
+    }
+  for (int q = 0; q < n; ++q) ent[q].tables = ent[ent[q].towner].tables;
   // Work lists of the persistent kernels, one per group: (configuration, chunk, i1, row block),
   // longest first.
   struct Item {
@@ -963,18 +1005,22 @@ int batched_impl(eprl_ctx *c, int n, const int *two_j, const int *dl,
       rp.i_lo2[e] = p.i[e].lo2;
       rp.i_n[e] = p.i[e].n;
     }
+    const Plan &tp = ent[ent[q].towner].plan;  // geometry of the tables it reads
     for (int e = 0; e < 4; ++e) {
-      rp.K_lo2[e] = p.K[e].lo2;
-      rp.K_n[e] = p.K[e].n;
+      rp.K_lo2[e] = tp.K[e].lo2;
+      rp.K_n[e] = tp.K[e].n;
     }
-    rp.X_lo2 = p.X.lo2;
-    rp.NX = p.X.n;
+    rp.X_lo2 = tp.X.lo2;
+    rp.NX = tp.X.n;
+    rp.tnd = tp.nd;
+    rp.xlo2 = p.X.lo2;
+    rp.xhi2 = p.X.lo2 + 2 * (p.X.n - 1);
     const double *tab = reinterpret_cast<const double *>(ws + ent[q].tables);
-    rp.U1 = tab + p.toff[0];
-    rp.U2 = tab + p.toff[1];
-    rp.U3 = tab + p.toff[2];
-    rp.U4 = tab + p.toff[3];
-    rp.U5 = tab + p.toff[4];
+    rp.U1 = tab + tp.toff[0];
+    rp.U2 = tab + tp.toff[1];
+    rp.U3 = tab + tp.toff[2];
+    rp.U4 = tab + tp.toff[3];
+    rp.U5 = tab + tp.toff[4];
     rp.B = boosters[q];
     rp.boff = reinterpret_cast<const int64_t *>(ws + ent[q].boff);
     rp.kr = reinterpret_cast<const int *>(ws + ent[q].kr);

@@ -99,8 +99,13 @@ struct RingParams {
   int two_j[10];
   int nd;
   int i_lo2[5], i_n[5];
+  // Index ranges of the ring tables U1..U5 (virtual spins, x) and the spin count tnd that strides
+  // them: the configuration's own, or those of a configuration of the same spins at a larger dl
+  // whose tables it shares (every index range of its own lies inside them).
   int K_lo2[4], K_n[4];
   int X_lo2, NX;
+  int tnd;
+  int xlo2, xhi2;         // the configuration's own x range (the loops' bounds)
   const double *U1, *U2, *U3, *U4, *U5;
   const double *B;
   const int64_t *boff;

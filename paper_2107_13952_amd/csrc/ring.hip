@@ -96,7 +96,7 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
   const int two_i1 = rp.i_lo2[0] + 2 * n1;
   const int d1 = rp.i_n[0], d2 = rp.i_n[1], d3 = rp.i_n[2], d4 = rp.i_n[3], d5 = rp.i_n[4];
   const int NX = rp.NX, nK2 = rp.K_n[0], nK3 = rp.K_n[1], nK4 = rp.K_n[2], nK5 = rp.K_n[3];
-  const int xhi_g = rp.X_lo2 + 2 * (NX - 1);
+  const int xhi_g = rp.xhi2, tnd = rp.tnd;
   const double *B = rp.B;
 
   // This thread's first step-1 item (u = tid): side 0 (T5, per l45) or 1 (T2, per l23).
@@ -189,8 +189,8 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
       }
     }
     // x closes (i1 l25 x); the other triads restrict the k ranges at each x.
-    const int xlo = imax(iabs(two_i1 - l25), rp.X_lo2), xhi = imin(two_i1 + l25, xhi_g);
-    const int64_t u3base = (((int64_t)o24 * nd + o34) * nd + o35) * NX;
+    const int xlo = imax(iabs(two_i1 - l25), rp.xlo2), xhi = imin(two_i1 + l25, xhi_g);
+    const int64_t u3base = (((int64_t)o24 * tnd + o34) * tnd + o35) * NX;
     // Active k4 and k3 windows at x (triads (k4 l35 x) and (k3 l24 x)); false if one is empty.
     auto windows = [&](int x, int &a4, int &b4, int &a3, int &b3) {
       a4 = imax(w4lo, iabs(l35 - x));
@@ -221,7 +221,7 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
         const int g0 = (ka - rp.K_lo2[3]) / 2, k4g = (k4 - rp.K_lo2[2]) / 2;
         kk0 = c > 0 ? (ka - lo5) / 2 : 0;
         pa = rp.U1 + (((int64_t)o25 * NX + xg) * d1 + n1) * nK5 + g0;
-        pb = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5 + g0) * nK4 + k4g;
+        pb = rp.U2 + ((((int64_t)o35 * tnd + o) * NX + xg) * nK5 + g0) * nK4 + k4g;
         sb = nK4;
       } else {
         const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
@@ -231,7 +231,7 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
         c = (n2 > 0 && ki < n3 && k3 >= a3 && k3 <= b3 && kb >= ka) ? (kb - ka) / 2 + 1 : 0;
         const int g0 = (ka - rp.K_lo2[0]) / 2, k3g = (k3 - rp.K_lo2[1]) / 2;
         kk0 = c > 0 ? (ka - lo2) / 2 : 0;
-        pa = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + k3g) * nK2 + g0;
+        pa = rp.U4 + ((((int64_t)o * tnd + o24) * NX + xg) * nK3 + k3g) * nK2 + g0;
         pb = rp.U5 + (((int64_t)o25 * NX + xg) * nK2 + g0) * d1 + n1;
         sb = d1;
       }
@@ -325,12 +325,12 @@ __device__ void ring_item(const RingParams &rp, int64_t chunk_index, int n1, int
         const int g0 = (f_lo - rp.K_lo2[3]) / 2, kg = (f_kc - rp.K_lo2[2]) / 2;
         f_pa = rp.U1 + ((int64_t)o25 * NX * d1 + n1) * nK5 + g0;                     // U1[o25][x][i1][k5]
         f_pax = (int64_t)d1 * nK5;
-        f_pb = rp.U2 + (((int64_t)o35 * nd + f_o) * NX * nK5 + g0) * nK4 + kg;        // U2[o35][o45][x][k5][k4]
+        f_pb = rp.U2 + (((int64_t)o35 * tnd + f_o) * NX * nK5 + g0) * nK4 + kg;        // U2[o35][o45][x][k5][k4]
         f_pbx = (int64_t)nK5 * nK4;
         f_sb = nK4;
       } else {
         const int g0 = (f_lo - rp.K_lo2[0]) / 2, kg = (f_kc - rp.K_lo2[1]) / 2;
-        f_pa = rp.U4 + (((int64_t)f_o * nd + o24) * NX * nK3 + kg) * nK2 + g0;        // U4[o23][o24][x][k3][k2]
+        f_pa = rp.U4 + (((int64_t)f_o * tnd + o24) * NX * nK3 + kg) * nK2 + g0;        // U4[o23][o24][x][k3][k2]
         f_pax = (int64_t)nK3 * nK2;
         f_pb = rp.U5 + ((int64_t)o25 * NX * nK2 + g0) * d1 + n1;                      // U5[o25][x][k2][i1]
         f_pbx = (int64_t)nK2 * d1;

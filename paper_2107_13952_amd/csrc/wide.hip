@@ -114,7 +114,7 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
   const int *J = rp.two_j;
   const int two_i1 = rp.i_lo2[0] + 2 * n1;
   const int NX = rp.NX, nK2 = rp.K_n[0], nK3 = rp.K_n[1], nK4 = rp.K_n[2], nK5 = rp.K_n[3];
-  const int xhi_g = rp.X_lo2 + 2 * (NX - 1);
+  const int xhi_g = rp.xhi2, tnd = rp.tnd;
   const double *B = rp.B;
 
   d4v acc[kMaxAcc];
@@ -180,8 +180,8 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
       }
     }
     if (w4hi < 0 || w3hi < 0) continue;  // uniform: no live shell in this core
-    const int xlo = imax(iabs(two_i1 - l25), rp.X_lo2), xhi = imin(two_i1 + l25, xhi_g);
-    const int64_t u3base = (((int64_t)o24 * nd + o34) * nd + o35) * NX;
+    const int xlo = imax(iabs(two_i1 - l25), rp.xlo2), xhi = imin(two_i1 + l25, xhi_g);
+    const int64_t u3base = (((int64_t)o24 * tnd + o34) * tnd + o35) * NX;
     auto windows = [&](int x, int &a4, int &b4, int &a3, int &b3) {
       a4 = imax(w4lo, iabs(l35 - x));
       b4 = imin(w4hi, l35 + x);
@@ -238,13 +238,13 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
           if (s5) {
             kgb = (lo - rp.K_lo2[3]) >> 1;
             P = rp.U1 + (((int64_t)o25 * NX + xg) * d1 + n1) * nK5;
-            Q = rp.U2 + (((int64_t)o35 * nd + o) * NX + xg) * nK5 * nK4 + ((lop + 2 * cc - rp.K_lo2[2]) >> 1);
+            Q = rp.U2 + (((int64_t)o35 * tnd + o) * NX + xg) * nK5 * nK4 + ((lop + 2 * cc - rp.K_lo2[2]) >> 1);
             sP = 1;
             sQ = nK4;
           } else {
             kgb = (lo - rp.K_lo2[0]) >> 1;
             P = rp.U5 + ((int64_t)o25 * NX + xg) * nK2 * d1 + n1;
-            Q = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + ((lop + 2 * cc - rp.K_lo2[1]) >> 1)) * nK2;
+            Q = rp.U4 + ((((int64_t)o * tnd + o24) * NX + xg) * nK3 + ((lop + 2 * cc - rp.K_lo2[1]) >> 1)) * nK2;
             sP = d1;
             sQ = 1;
           }

@@ -339,6 +339,27 @@ def test_shell_scan(lib, torch, two_j, dl_max, seed):
     assert torch.equal(again, scan)
 
 
+def test_shell_scan_full_size(lib, torch):
+    """The scan of the j = 3 vertex over dl = 0..8 (its levels read the 6j tables of dl = 8):
+    every level bitwise equal to the plain call on its own packed boosters (which builds its own
+    tables), and the dl = 8 level equal to the stored oracle tensor when present."""
+    import os
+    cfg = workloads.CFG2
+    two_j, dl_max = cfg["two_j"], cfg["dl"]
+    b, bd = boosters_for(torch, two_j, dl_max, cfg["booster_seed"])
+    note(f"shell scan {two_j} dl_max={dl_max} (full size)")
+    scan = lib.vertex_tensor_scan(two_j, dl_max, 1.2, bd)
+    for dl in range(dl_max + 1):
+        plain = lib.vertex_tensor(two_j, dl, 1.2, torch.from_numpy(sub_boosters(two_j, dl_max, dl, b)).cuda())
+        assert torch.equal(plain, scan[dl]), dl
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"vertex_{cfg['name']}.npz")
+    if os.path.exists(path):
+        g = np.load(path)
+        assert list(g["two_j"]) == two_j and int(g["dl"]) == dl_max
+        assert int(g["booster_seed"]) == cfg["booster_seed"]
+        assert normwise(scan[dl_max].cpu().numpy(), g["A"]) <= TOL
+
+
 def test_cfg2_full_size(lib, torch):
     """j = 3, dl = 8 at full size, in the launch configuration of the benchmark: the
     per-shell path on a contiguous block of shells against the oracle; both paths on the full
