@@ -358,6 +358,10 @@ int triad_count(int lo, int n, int a, int x) {
 // blocks and the eight wavefronts of a workgroup: wavefront w holds the tiles w + 8 j of its
 // block and runs them in groups of three (the last group of the fourteen holds two), a group
 // whole once it holds one of them.
+// k steps of four the wide kernel's T stage multiplies for a spin value with s active steps:
+// three unconditionally, the last two when the fourth is active.
+static int t_steps(int s) { return s <= 3 ? 3 : 5; }
+
 static int wide_update_tiles(int RT, int CT, int nrb) {
   const int RTb = (RT + nrb - 1) / nrb;
   int total = 0;
@@ -470,26 +474,29 @@ void count_work(const Plan &p, double out[5]) {
               const int s3 = ((b3 - w3lo) / 2) / 4 - ((a3 - w3lo) / 2) / 4 + 1;
               if (p.ring_cls == kWideClass) {
                 // Every stage on 16x16x4 tiles (2048 flops each): T5 / T2 over the active k5 /
-                // k2 values in steps of 4, G / H per active k4 / k3 over the spin values in
+                // k2 values in steps of 4 (at least three steps, else five), G / H per k4 / k3
+                // position of the windows rounded out to multiples of 4 over the spin values in
                 // steps of 4 (repeated per row block), P over the row tiles and one or two k3
-                // column tiles, the update over all row and column tiles.
+                // column tiles, the update over the wavefronts' groups of tiles.
                 int tsteps = 0;
                 for (int o = 0; o < nd && o < 64; ++o) {
                   if (n5[o] > 0) {
                     const int ka = std::max(lo5[o], std::abs(x - J[L14]));
                     const int kb = std::min(lo5[o] + 2 * (n5[o] - 1), x + J[L14]);
-                    if (kb >= ka) tsteps += ((kb - lo5[o]) / 2) / 4 - ((ka - lo5[o]) / 2) / 4 + 1;
+                    if (kb >= ka) tsteps += t_steps(((kb - lo5[o]) / 2) / 4 - ((ka - lo5[o]) / 2) / 4 + 1);
                   }
                   if (n2[o] > 0) {
                     const int ka = std::max(lo2[o], std::abs(J[L13] - x));
                     const int kb = std::min(lo2[o] + 2 * (n2[o] - 1), J[L13] + x);
-                    if (kb >= ka) tsteps += ((kb - lo2[o]) / 2) / 4 - ((ka - lo2[o]) / 2) / 4 + 1;
+                    if (kb >= ka) tsteps += t_steps(((kb - lo2[o]) / 2) / 4 - ((ka - lo2[o]) / 2) / 4 + 1);
                   }
                 }
                 const int RT = (d5 * d4 + 15) / 16, CT = (d3 * d2 + 15) / 16;
                 const int nq = ((((b3 - w3lo) / 2) | 3) + 16) / 16;
                 const int upd_tiles = wide_update_tiles(RT, CT, p.ring_nrb);
-                const double per_block = tsteps + (double)(na4 + na3) * ((nd + 3) / 4);
+                const int nG = (((b4 - w4lo) / 2) | 3) - (((a4 - w4lo) / 2) & ~3) + 1;
+                const int nH = (((b3 - w3lo) / 2) | 3) - (((a3 - w3lo) / 2) & ~3) + 1;
+                const double per_block = tsteps + (double)(nG + nH) * ((nd + 3) / 4);
                 executed += 2048.0 * (p.ring_nrb * per_block + (double)RT * nq * s4 + (double)upd_tiles * s3);
               } else {
                 executed += 2.0 * rows * KW * 4 * s4 + 2.0 * rows * cols * 4 * s3;

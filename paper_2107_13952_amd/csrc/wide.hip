@@ -261,9 +261,13 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
             av[s] = (kin && rowok) ? a : 0.0;
             bv[s] = (kin && colok) ? b : 0.0;
           }
+          // Steps 0..2 unconditionally (zero operands past ib), 3..4 when active.
 #pragma unroll
-          for (int s = 0; s < TS; ++s)
-            if (kk0 + 4 * s <= ib) t = mfma(av[s], bv[s], t);
+          for (int s = 0; s < 3; ++s) t = mfma(av[s], bv[s], t);
+          if (kk0 + 12 <= ib) {  // uniform
+#pragma unroll
+            for (int s = 3; s < TS; ++s) t = mfma(av[s], bv[s], t);
+          }
         }
         double *Ts = s5 ? T5s : T2s;
 #pragma unroll
@@ -331,8 +335,7 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
           for (int s = 0; s < GS3; ++s) {
             if (4 * s >= nd) break;  // uniform
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-              if (act[q]) t[q] = mfma(av[q][s], bv[q][s], t[q]);
+            for (int q = 0; q < 2; ++q) t[q] = mfma(av[q][s], bv[q][s], t[q]);  // zero operands when idle
           }
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
