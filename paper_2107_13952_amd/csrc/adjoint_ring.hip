@@ -101,7 +101,8 @@ __host__ __device__ inline AdjGeom adj_geom(int nd, int kl, int iw, int kw, int 
   return g;
 }
 
-__global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs psi, double *gbuf,
+__global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const int *__restrict__ order,
+                                                          PsiPtrs psi, double *gbuf,
                                                           int KLr, int IWr, int KWr, int NGr) {
   extern __shared__ double sm[];
   const int nd = rp.nd, nd3 = nd * nd * nd;
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, PsiPtrs
   int64_t *bo = reinterpret_cast<int64_t *>(rng + 8 * nd);
 
   const int tid = threadIdx.x;
-  const int core = blockIdx.x;
+  const int core = order[blockIdx.x];  // cores longest first
   const int o24 = core / nd3, o25 = (core / (nd * nd)) % nd, o34 = (core / nd) % nd, o35 = core % nd;
   const int *J = rp.two_j;
   const int l24 = J[L24] + 2 * o24, l25 = J[L25] + 2 * o25, l35 = J[L35] + 2 * o35;
@@ -475,6 +476,49 @@ void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw, int &ng) {
   while (ng < nd && adj_geom(nd, kl, iw, kw, ng + 1).bytes <= cap) ++ng;
 }
 
+void adjoint_ring_order(const Plan &p, std::vector<int> &order) {
+  const int nd = p.nd, nd3 = nd * nd * nd, ncore = nd * nd3;
+  const int *J = p.two_j;
+  const int i1lo = p.i[0].lo2, i1hi = p.i[0].lo2 + 2 * (p.i[0].n - 1);
+  const int xhi_g = p.X.lo2 + 2 * (p.X.n - 1);
+  std::vector<double> cost(ncore, 0.0);
+  for (int core = 0; core < ncore; ++core) {
+    const int o24 = core / nd3, o25 = (core / (nd * nd)) % nd, o34 = (core / nd) % nd, o35 = core % nd;
+    int w4lo = 1 << 30, w4hi = -1, w3lo = 1 << 30, w3hi = -1, width = 0;
+    for (int o = 0; o < nd; ++o) {
+      const int t5 = (o25 * nd + o35) * nd + o, t4 = (o * nd + o24) * nd + o34;
+      const int t2 = (o * nd + o24) * nd + o25, t3 = (o34 * nd + o35) * nd + o;
+      const int n5 = p.kr[(3 * nd3 + t5) * 2 + 1], n4 = p.kr[(2 * nd3 + t4) * 2 + 1];
+      const int n2 = p.kr[(0 * nd3 + t2) * 2 + 1], n3 = p.kr[(1 * nd3 + t3) * 2 + 1];
+      if (n5 > 0 && n4 > 0) {
+        const int l4 = p.kr[(2 * nd3 + t4) * 2];
+        w4lo = std::min(w4lo, l4);
+        w4hi = std::max(w4hi, l4 + 2 * (n4 - 1));
+        width += n5 + n4;
+      }
+      if (n2 > 0 && n3 > 0) {
+        const int l3 = p.kr[(1 * nd3 + t3) * 2];
+        w3lo = std::min(w3lo, l3);
+        w3hi = std::max(w3hi, l3 + 2 * (n3 - 1));
+        width += n2 + n3;
+      }
+    }
+    if (w4hi < 0 || w3hi < 0) continue;
+    const int l24 = J[L24] + 2 * o24, l25 = J[L25] + 2 * o25, l35 = J[L35] + 2 * o35;
+    const int xlo = std::max(p.X.lo2, l25 > i1hi ? l25 - i1hi : (i1lo > l25 ? i1lo - l25 : ((l25 - i1lo) & 1)));
+    const int xhi = std::min(xhi_g, i1hi + l25);
+    int nx = 0;
+    for (int x = xlo; x <= xhi; x += 2)
+      if (std::max(w4lo, std::abs(l35 - x)) <= std::min(w4hi, l35 + x) &&
+          std::max(w3lo, std::abs(l24 - x)) <= std::min(w3hi, l24 + x))
+        ++nx;
+    cost[core] = (double)nx * (1 + width);
+  }
+  order.resize(ncore);
+  for (int k = 0; k < ncore; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+}
+
 size_t adjoint_ring_smem(int nd, int kl, int iw, int kw, int ng) { return adj_geom(nd, kl, iw, kw, ng).bytes; }
 size_t adjoint_ring_gbuf_bytes(int nd, int kl) {
   return sizeof(double) * 2 * (size_t)nd * nd * nd * nd * 4 * nd * kl;
@@ -486,14 +530,14 @@ hipError_t adjoint_ring_init_attributes() {
 }
 
 hipError_t launch_adjoint_ring(const RingParams &rp, int kl, int iw, int kw, int ng,
-                               const double *const psi[5], double *gbuf, int64_t total, double gre,
-                               double gim, double *grad_b, hipStream_t s) {
+                               const int *order, const double *const psi[5], double *gbuf,
+                               int64_t total, double gre, double gim, double *grad_b, hipStream_t s) {
   PsiPtrs pp;
   for (int a = 0; a < 5; ++a) pp.p[a] = psi[a];
   const int nd = rp.nd;
   const size_t bytes = adj_geom(nd, kl, iw, kw, ng).bytes;
   if (nd > kAdjRingMaxNd || ng < 1 || bytes > kAdjRingMaxLds) return hipErrorInvalidValue;
-  adjoint_ring_kernel<<<nd * nd * nd * nd, AT, bytes, s>>>(rp, pp, gbuf, kl, iw, kw, ng);
+  adjoint_ring_kernel<<<nd * nd * nd * nd, AT, bytes, s>>>(rp, order, pp, gbuf, kl, iw, kw, ng);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (total <= 0) return hipSuccess;

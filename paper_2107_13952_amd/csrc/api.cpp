@@ -94,6 +94,7 @@ struct eprl_ctx {
   // Cost schedule of the last configuration run in the factorised order (host data only; it
   // depends on the spins, dl and the workgroup target, and is recomputed when they change).
   std::vector<int> sched_key, sched_bounds;
+  std::vector<int> adj_order_key, adj_order;  // launch order of the factorised adjoint's cores
   int sched_nchunk = 0;
   // Plan of the last configuration asked for (host data only, keyed by spins and dl).
   std::vector<int> plan_key;
@@ -1523,15 +1524,23 @@ int eprl_contract_boundary_adjoint(eprl_ctx *c, const int two_j[10], int dl, con
   if (c->algo != EPRL_ALGO_SHELL && probe.ring_KW != 0 && probe.nd <= kAdjRingMaxNd)
     adjoint_ring_dims(probe, akl, aiw, akw, ang);
   if (akl > 0 && adjoint_ring_smem(probe.nd, akl, aiw, akw, ang) <= kAdjRingMaxLds) {
-    // Factorised order: per-core G vectors, then a fixed-order sum per booster entry.
+    // Factorised order: per-core G vectors, then a fixed-order sum per booster entry.  The
+    // cores' launch order (longest first) is uploaded with the plan.
+    std::vector<int> key(two_j, two_j + 10);
+    key.push_back(dl);
+    if (key != c->adj_order_key) {
+      adjoint_ring_order(probe, c->adj_order);
+      c->adj_order_key = key;
+    }
     Prepared prep;
     rc = prepare(c, two_j, dl, align_up(adjoint_ring_gbuf_bytes(probe.nd, akl), 256), prep, true,
-                 nullptr, &probe);
+                 &c->adj_order, &probe);
     if (rc) return rc;
     RingParams rp = ring_params(prep, B);
     TimedLaunch tl(c, 3);
-    HIP_TRY(c, launch_adjoint_ring(rp, akl, aiw, akw, ang, psi, reinterpret_cast<double *>(prep.tail),
-                                   prep.plan.boff.back(), grad_F[0], grad_F[1], grad_boosters, c->stream));
+    HIP_TRY(c, launch_adjoint_ring(rp, akl, aiw, akw, ang, prep.sched, psi,
+                                   reinterpret_cast<double *>(prep.tail), prep.plan.boff.back(),
+                                   grad_F[0], grad_F[1], grad_boosters, c->stream));
     return EPRL_OK;
   }
   const int kpad = std::max(probe.kmax, 1);

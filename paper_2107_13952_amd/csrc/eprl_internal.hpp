@@ -292,10 +292,14 @@ constexpr size_t kAdjRingMaxLds = 160 * 1024 - 256;
 void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw, int &ng);
 size_t adjoint_ring_smem(int nd, int kl, int iw, int kw, int ng);
 size_t adjoint_ring_gbuf_bytes(int nd, int kl);
+// Launch order of the adjoint's cores, longest first by an estimate of their work (the x values
+// with both core windows non-empty, times the windows' widths), so that the last workgroups to
+// start are short ones; every core writes its own G vectors, so the order changes no result.
+void adjoint_ring_order(const Plan &p, std::vector<int> &order);
 hipError_t adjoint_ring_init_attributes();
 hipError_t launch_adjoint_ring(const RingParams &rp, int kl, int iw, int kw, int ng,
-                               const double *const psi[5], double *gbuf, int64_t total, double gre,
-                               double gim, double *grad_b, hipStream_t s);
+                               const int *order, const double *const psi[5], double *gbuf,
+                               int64_t total, double gre, double gim, double *grad_b, hipStream_t s);
 hipError_t launch_adjoint_reduce(const AdjointParams &ap, int64_t total, double gre, double gim,
                                  double *grad_b, hipStream_t s);
 
