@@ -48,6 +48,17 @@ __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
 constexpr int AT = 512;  // threads per workgroup
 
+// Division by a size that is the same for the whole kernel, as a multiply-high by the rounded-up
+// reciprocal: exact for dividends and divisors below 2^16 (the item indices of the loops below),
+// and one instruction where the generic integer division takes dozens.
+struct FastDiv {
+  uint32_t m;
+  int d;
+  __device__ explicit FastDiv(int d_)
+      : m(d_ > 1 ? (uint32_t)((0x100000000ull + (uint64_t)d_ - 1) / (uint64_t)d_) : 0u), d(d_) {}
+  __device__ int operator()(int q) const { return d > 1 ? (int)__umulhi((uint32_t)q, m) : q; }
+};
+
 // The five boundary vectors (device, complex interleaved), passed by value.
 struct PsiPtrs {
   const double *p[5];
@@ -108,6 +119,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
   const int nd = rp.nd, nd3 = nd * nd * nd;
   const AdjGeom geo = adj_geom(nd, KLr, IWr, KWr, NGr);
   const int kl = geo.kl, iw = geo.iw, kw = geo.kw, ng = geo.ng;
+  const FastDiv by_kw(kw), by_kl(kl), by_iw(iw), by_kliw(kl * iw), by_2kliw(2 * kl * iw);
   cplx *cs = reinterpret_cast<cplx *>(sm);
   cplx *P1 = cs + geo.p1, *u5 = cs + geo.u5, *u4 = cs + geo.u4, *u2 = cs + geo.u2, *u3 = cs + geo.u3;
   cplx *G5 = cs + geo.g5, *G4 = cs + geo.g4, *G3 = cs + geo.g3, *G2 = cs + geo.g2;
@@ -207,7 +219,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
     __syncthreads();  // previous x's readers are done
     // Table slices of this x: U1(i1, k5), U5(k2, i1), U3(k4, k3) over the core windows.
     for (int q = tid; q < iw * kw; q += AT) {
-      const int i = q / kw, p = q % kw;
+      const int i = by_kw(q), p = q - i * kw;
       double v1 = 0.0, v5 = 0.0;
       if (i < d1 && p < nw5)
         v1 = rp.U1[(((int64_t)o25 * NX + xg) * d1 + i) * nK5 + ((w5lo - rp.K_lo2[3]) >> 1) + p];
@@ -217,7 +229,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
       U5s[p * iw + i] = v5;
     }
     for (int q = tid; q < kw * kw; q += AT) {
-      const int p4 = q / kw, p3 = q % kw;
+      const int p4 = by_kw(q), p3 = q - p4 * kw;
       double v = 0.0;
       if (p4 < nw4 && p3 < nw3)
         v = rp.U3[((u3base + xg) * nK4 + ((w4lo - rp.K_lo2[2]) >> 1) + p4) * nK3 +
@@ -227,7 +239,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
     __syncthreads();
     // V2_o(k3, i1) = sum_k2 U4(k3, k2; o) u2(k2; o) U5(k2, i1) for every l23 = o.
     for (int q = tid; q < nd * kl * iw; q += AT) {
-      const int o = q / (kl * iw), k3i = (q / iw) % kl, i = q % iw;
+      const int o = by_kliw(q), rr = q - o * (kl * iw), k3i = by_iw(rr), i = rr - k3i * iw;
       const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
       cplx v{0.0, 0.0};
       if (k3i < n3 && i < d1) {
@@ -244,7 +256,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
     __syncthreads();
     // X2(k3, i1) = sum_o u3(k3; o) V2_o(k3, i1), k3 over the core window.
     for (int q = tid; q < kw * iw; q += AT) {
-      const int p3 = q / iw, i = q % iw;
+      const int p3 = by_iw(q), i = q - p3 * iw;
       cplx v{0.0, 0.0};
       if (p3 < nw3) {
         const int k3 = w3lo + 2 * p3;
@@ -258,7 +270,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
     __syncthreads();
     // R4(k4, i1) = sum_k3 U3(k4, k3) X2(k3, i1); X5 cleared.
     for (int q = tid; q < kw * iw; q += AT) {
-      const int p4 = q / iw, i = q % iw;
+      const int p4 = by_iw(q), i = q - p4 * iw;
       cplx v{0.0, 0.0};
       if (p4 < nw4)
         for (int p3 = 0; p3 < nw3; ++p3) v = cfma(v, X2[p3 * iw + i], U3s[p4 * kw + p3]);
@@ -272,27 +284,30 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
       // Z5_o(i1, k4) = p1(i1) sum_k5 U1(i1, k5) u5(k5) U2(k5, k4);  Q5_o(k5, i1) = sum_k4 U2(k5, k4)
       // u4(k4) R4(k4, i1), for every o of the group.
       for (int q = tid; q < gn * 2 * iw * kl; q += AT) {
-        const int gi = q / (2 * iw * kl), r = q - gi * (2 * iw * kl), o = og + gi;
+        const int gi = by_2kliw(q), r = q - gi * (2 * iw * kl), o = og + gi;
         const int lo5 = rng[0 * nd + o], n5 = rng[1 * nd + o], lo4 = rng[2 * nd + o], n4 = rng[3 * nd + o];
         const int p5 = (lo5 - w5lo) >> 1, p4 = (lo4 - w4lo) >> 1;
         const double *u2b = rp.U2 + ((((int64_t)o35 * nd + o) * NX + xg) * nK5 + ((lo5 - rp.K_lo2[3]) >> 1)) * nK4 +
                             ((lo4 - rp.K_lo2[2]) >> 1);
         cplx v{0.0, 0.0};
         if (r < iw * kl) {
-          const int i = r / kl, k4i = r % kl;
+          const int i = by_kl(r), k4i = r - i * kl;
           if (i < d1 && k4i < n4) {
+            const double *u2c = u2b + k4i;  // column k4i of U2, advanced a row (nK4) per k5
 #pragma unroll 4
-            for (int k5i = 0; k5i < n5; ++k5i)
-              v = cfma(v, u5[o * kl + k5i], U1s[i * kw + p5 + k5i] * u2b[(int64_t)k5i * nK4 + k4i]);
+            for (int k5i = 0; k5i < n5; ++k5i, u2c += nK4)
+              v = cfma(v, u5[o * kl + k5i], U1s[i * kw + p5 + k5i] * *u2c);
             v = cmul(v, P1[i]);
           }
           Z5[gi * iw * kl + r] = v;
         } else {
-          const int r2 = r - iw * kl, k5i = r2 / iw, i = r2 % iw;
-          if (k5i < n5 && i < d1)
+          const int r2 = r - iw * kl, k5i = by_iw(r2), i = r2 - k5i * iw;
+          if (k5i < n5 && i < d1) {
+            const double *u2r = u2b + (int64_t)k5i * nK4;  // row k5i of U2
 #pragma unroll 4
             for (int k4i = 0; k4i < n4; ++k4i)
-              v = cadd(v, cmul(u4[o * kl + k4i], cscale(R4[(p4 + k4i) * iw + i], u2b[(int64_t)k5i * nK4 + k4i])));
+              v = cadd(v, cmul(u4[o * kl + k4i], cscale(R4[(p4 + k4i) * iw + i], u2r[k4i])));
+          }
           Q5[gi * kl * iw + r2] = v;
         }
       }
@@ -301,7 +316,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
       // X5(i1, k4) += Z5_o(i1, k4) u4_o(k4), the group's o in increasing order.
       for (int q = tid; q < gn * 2 * kl + iw * kw; q += AT) {
         if (q < gn * kl) {
-          const int gi = q / kl, k4i = q - gi * kl, o = og + gi;
+          const int gi = by_kl(q), k4i = q - gi * kl, o = og + gi;
           const int n4 = rng[3 * nd + o], p4 = (rng[2 * nd + o] - w4lo) >> 1;
           if (k4i < n4) {
             cplx v{0.0, 0.0};
@@ -309,7 +324,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
             G4[o * kl + k4i] = cadd(G4[o * kl + k4i], v);
           }
         } else if (q < gn * 2 * kl) {
-          const int qq = q - gn * kl, gi = qq / kl, k5i = qq - gi * kl, o = og + gi;
+          const int qq = q - gn * kl, gi = by_kl(qq), k5i = qq - gi * kl, o = og + gi;
           const int n5 = rng[1 * nd + o], p5 = (rng[0 * nd + o] - w5lo) >> 1;
           if (k5i < n5) {
             cplx v{0.0, 0.0};
@@ -318,7 +333,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
             G5[o * kl + k5i] = cadd(G5[o * kl + k5i], v);
           }
         } else {
-          const int r = q - gn * 2 * kl, i = r / kw, p = r - i * kw;
+          const int r = q - gn * 2 * kl, i = by_kw(r), p = r - i * kw;
           if (i < d1) {
             cplx v = X5[r];
             for (int gi = 0; gi < gn; ++gi) {
@@ -333,7 +348,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
     }
     // R3(i1, k3) = sum_k4 X5(i1, k4) U3(k4, k3)
     for (int q = tid; q < iw * kw; q += AT) {
-      const int i = q / kw, p3 = q % kw;
+      const int i = by_kw(q), p3 = q - i * kw;
       cplx v{0.0, 0.0};
       if (p3 < nw3)
         for (int p4 = 0; p4 < nw4; ++p4) v = cfma(v, X5[i * kw + p4], U3s[p4 * kw + p3]);
@@ -346,7 +361,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
       // G3_o(k3) += sum_i1 R3(i1, k3) V2_o(k3, i1);  S2_o(i1, k2) = sum_k3 R3(i1, k3) u3(k3) U4(k3, k2)
       for (int q = tid; q < gn * (kl + iw * kl); q += AT) {
         if (q < gn * kl) {
-          const int gi = q / kl, k3i = q - gi * kl, o = og + gi;
+          const int gi = by_kl(q), k3i = q - gi * kl, o = og + gi;
           const int n3 = rng[7 * nd + o], p3 = (rng[6 * nd + o] - w3lo) >> 1;
           if (k3i < n3) {
             cplx v{0.0, 0.0};
@@ -354,17 +369,18 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
             G3[o * kl + k3i] = cadd(G3[o * kl + k3i], v);
           }
         } else {
-          const int qq = q - gn * kl, gi = qq / (iw * kl), r = qq - gi * (iw * kl), o = og + gi;
+          const int qq = q - gn * kl, gi = by_kliw(qq), r = qq - gi * (iw * kl), o = og + gi;
           const int lo2 = rng[4 * nd + o], n2 = rng[5 * nd + o], lo3 = rng[6 * nd + o], n3 = rng[7 * nd + o];
           const int p3 = (lo3 - w3lo) >> 1;
-          const int i = r / kl, k2i = r % kl;
+          const int i = by_kl(r), k2i = r - i * kl;
           cplx v{0.0, 0.0};
           if (i < d1 && k2i < n2) {
             const double *u4b = rp.U4 + ((((int64_t)o * nd + o24) * NX + xg) * nK3 + ((lo3 - rp.K_lo2[1]) >> 1)) * nK2 +
                                 ((lo2 - rp.K_lo2[0]) >> 1);
+            const double *u4c = u4b + k2i;  // column k2i of U4, advanced a row (nK2) per k3
 #pragma unroll 4
-            for (int k3i = 0; k3i < n3; ++k3i)
-              v = cadd(v, cmul(u3[o * kl + k3i], cscale(R3[i * kw + p3 + k3i], u4b[(int64_t)k3i * nK2 + k2i])));
+            for (int k3i = 0; k3i < n3; ++k3i, u4c += nK2)
+              v = cadd(v, cmul(u3[o * kl + k3i], cscale(R3[i * kw + p3 + k3i], *u4c)));
           }
           S2[gi * iw * kl + r] = v;
         }
@@ -372,7 +388,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
       __syncthreads();
       // G2_o(k2) += sum_i1 S2_o(i1, k2) U5(k2, i1)
       for (int q = tid; q < gn * kl; q += AT) {
-        const int gi = q / kl, k2i = q - gi * kl, o = og + gi;
+        const int gi = by_kl(q), k2i = q - gi * kl, o = og + gi;
         const int n2 = rng[5 * nd + o], p2 = (rng[4 * nd + o] - w2lo) >> 1;
         if (k2i < n2) {
           cplx v{0.0, 0.0};
