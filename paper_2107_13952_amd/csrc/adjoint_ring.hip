@@ -211,31 +211,54 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
     xlo = imax(rp.X_lo2, l25 > i1hi ? l25 - i1hi : (i1lo > l25 ? i1lo - l25 : ((l25 - i1lo) & 1)));
     xhi = imin(xhi_g, i1hi + l25);
   }
-  for (int x = xlo; x <= xhi; x += 2) {
+  // x values with both core windows non-empty, in increasing order.
+  auto active = [&](int x) {
+    return imax(w4lo, iabs(l35 - x)) <= imin(w4hi, l35 + x) && imax(w3lo, iabs(l24 - x)) <= imin(w3hi, l24 + x);
+  };
+  auto next_active = [&](int x) {
+    while (x <= xhi && !active(x)) x += 2;
+    return x;
+  };
+  // Table slices of an x (U1(i1, k5), U5(k2, i1), U3(k4, k3) over the core windows), read into
+  // registers one x ahead of their use: this thread's entries q = tid (U1, U5) and tid, tid + AT
+  // (U3) of the slices (iw kw <= AT and kw kw <= 2 AT, checked at launch).
+  double pf1 = 0.0, pf5 = 0.0, pf3[2] = {0.0, 0.0};
+  auto fetch = [&](int x) {
+    const int xg = (x - rp.X_lo2) / 2;
+    pf1 = pf5 = 0.0;
+    if (tid < iw * kw) {
+      const int i = by_kw(tid), p = tid - i * kw;
+      if (i < d1 && p < nw5)
+        pf1 = rp.U1[(((int64_t)o25 * NX + xg) * d1 + i) * nK5 + ((w5lo - rp.K_lo2[3]) >> 1) + p];
+      if (i < d1 && p < nw2)
+        pf5 = rp.U5[(((int64_t)o25 * NX + xg) * nK2 + ((w2lo - rp.K_lo2[0]) >> 1) + p) * d1 + i];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = tid + h * AT, p4 = by_kw(q), p3 = q - p4 * kw;
+      pf3[h] = 0.0;
+      if (q < kw * kw && p4 < nw4 && p3 < nw3)
+        pf3[h] = rp.U3[((u3base + xg) * nK4 + ((w4lo - rp.K_lo2[2]) >> 1) + p4) * nK3 +
+                       ((w3lo - rp.K_lo2[1]) >> 1) + p3];
+    }
+  };
+  int x = live ? next_active(xlo) : xhi + 2;
+  if (x <= xhi) fetch(x);
+  while (x <= xhi) {
     const int a4 = imax(w4lo, iabs(l35 - x)), b4 = imin(w4hi, l35 + x);
     const int a3 = imax(w3lo, iabs(l24 - x)), b3 = imin(w3hi, l24 + x);
-    if (a4 > b4 || a3 > b3) continue;  // uniform
     const int xg = (x - rp.X_lo2) / 2;
+    const int xn = next_active(x + 2);
     __syncthreads();  // previous x's readers are done
-    // Table slices of this x: U1(i1, k5), U5(k2, i1), U3(k4, k3) over the core windows.
-    for (int q = tid; q < iw * kw; q += AT) {
-      const int i = by_kw(q), p = q - i * kw;
-      double v1 = 0.0, v5 = 0.0;
-      if (i < d1 && p < nw5)
-        v1 = rp.U1[(((int64_t)o25 * NX + xg) * d1 + i) * nK5 + ((w5lo - rp.K_lo2[3]) >> 1) + p];
-      if (i < d1 && p < nw2)
-        v5 = rp.U5[(((int64_t)o25 * NX + xg) * nK2 + ((w2lo - rp.K_lo2[0]) >> 1) + p) * d1 + i];
-      U1s[i * kw + p] = v1;
-      U5s[p * iw + i] = v5;
+    if (tid < iw * kw) {
+      const int i = by_kw(tid), p = tid - i * kw;
+      U1s[i * kw + p] = pf1;
+      U5s[p * iw + i] = pf5;
     }
-    for (int q = tid; q < kw * kw; q += AT) {
-      const int p4 = by_kw(q), p3 = q - p4 * kw;
-      double v = 0.0;
-      if (p4 < nw4 && p3 < nw3)
-        v = rp.U3[((u3base + xg) * nK4 + ((w4lo - rp.K_lo2[2]) >> 1) + p4) * nK3 +
-                  ((w3lo - rp.K_lo2[1]) >> 1) + p3];
-      U3s[q] = v;
-    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (tid + h * AT < kw * kw) U3s[tid + h * AT] = pf3[h];
+    if (xn <= xhi) fetch(xn);  // in flight during this x's stages
     __syncthreads();
     // V2_o(k3, i1) = sum_k2 U4(k3, k2; o) u2(k2; o) U5(k2, i1) for every l23 = o.
     for (int q = tid; q < nd * kl * iw; q += AT) {
@@ -398,6 +421,7 @@ __global__ __launch_bounds__(AT) void adjoint_ring_kernel(RingParams rp, const i
       }
       __syncthreads();
     }
+    x = xn;
   }
   __syncthreads();
   // gbuf[core][slot][o][k], slots in booster-edge order: 0 G2, 1 G3, 2 G4, 3 G5.
@@ -490,6 +514,8 @@ void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw, int &ng) {
   const size_t cap = adj_geom(nd, kl, iw, kw, 1).bytes <= two ? two : kAdjRingMaxLds;
   ng = 1;
   while (ng < nd && adj_geom(nd, kl, iw, kw, ng + 1).bytes <= cap) ++ng;
+  // Each thread holds one U1/U5 entry and two U3 entries of the next x's slices.
+  if (iw * kw > AT || kw * kw > 2 * AT) kl = 0;
 }
 
 void adjoint_ring_order(const Plan &p, std::vector<int> &order) {
@@ -553,6 +579,7 @@ hipError_t launch_adjoint_ring(const RingParams &rp, int kl, int iw, int kw, int
   const int nd = rp.nd;
   const size_t bytes = adj_geom(nd, kl, iw, kw, ng).bytes;
   if (nd > kAdjRingMaxNd || ng < 1 || bytes > kAdjRingMaxLds) return hipErrorInvalidValue;
+  if (iw * kw > AT || kw * kw > 2 * AT) return hipErrorInvalidValue;  // the slices' prefetch
   adjoint_ring_kernel<<<nd * nd * nd * nd, AT, bytes, s>>>(rp, order, pp, gbuf, kl, iw, kw, ng);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -288,7 +288,7 @@ constexpr int kAdjRingMaxNd = 11;
 constexpr size_t kAdjRingMaxLds = 160 * 1024 - 256;
 // LDS sizes of the kernel for a configuration: kl = largest k range of a spin, iw = number of i1
 // values, kw = widest core window of k5, k4 (over l45), k3 or k2 (over l23), ng = spins per group
-// of the two halves.
+// of the two halves.  kl = 0 when the windows are too wide for the kernel.
 void adjoint_ring_dims(const Plan &p, int &kl, int &iw, int &kw, int &ng);
 size_t adjoint_ring_smem(int nd, int kl, int iw, int kw, int ng);
 size_t adjoint_ring_gbuf_bytes(int nd, int kl);
