@@ -23,6 +23,8 @@
 // core's weighted booster blocks; the other 6j values (and booster entries otherwise) are read
 // from global memory (L1/L2) straight into the MFMA operands.  Stages are separated by workgroup
 // barriers.
+#include <type_traits>
+
 #include "eprl_internal.hpp"
 
 namespace eprl {
@@ -220,8 +222,10 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
       // A operand: the booster block M5 (M2) of that spin, row c; B operand: the product of the
       // two 6j columns, column c the k4 (k3) of that spin's range.  All loads of a task are issued
       // before its multiply-adds (addresses clamped into range, values masked afterwards).
-      for (int u = w; u < 2 * nd; u += WW) {
-        const bool s5 = u < nd;
+      // The two sides as two copies of the task (the side is uniform per task): strides and
+      // table pointers known per copy.
+      auto t_task = [&](int u, auto side) {
+        constexpr bool s5 = decltype(side)::value;
         const int o = s5 ? u : u - nd;
         const int lo = rng[(s5 ? 0 : 4) * nd + o], n = rng[(s5 ? 1 : 5) * nd + o];
         const int lop = rng[(s5 ? 2 : 6) * nd + o], np = rng[(s5 ? 3 : 7) * nd + o];
@@ -258,8 +262,10 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
             const double a = STG ? Mb[((s5 ? 0 : 2) * nd + o) * 256 + cr * 16 + kc]
                                  : bm[kc] * (double)(lo + 2 * kc + 1);
             const double b = P[(int64_t)(kgb + kc) * sP] * Q[(int64_t)(kgb + kc) * sQ];
-            av[s] = (kin && rowok) ? a : 0.0;
-            bv[s] = (kin && colok) ? b : 0.0;
+            // k values outside [ia, ib] add nothing: zeroing one (finite) operand is enough.  Rows
+            // c >= d5 (d2) and columns c >= np of T read clamped entries and are never used.
+            av[s] = kin ? a : 0.0;
+            bv[s] = b;
           }
           // Steps 0..2 unconditionally (zero operands past ib), 3..4 when active.
 #pragma unroll
@@ -272,6 +278,12 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
         double *Ts = s5 ? T5s : T2s;
 #pragma unroll
         for (int r = 0; r < 4; ++r) Ts[(o * 16 + g + 4 * r) * 16 + c] = t[r];
+      };
+      for (int u = w; u < 2 * nd; u += WW) {
+        if (u < nd)
+          t_task(u, std::true_type{});
+        else
+          t_task(u, std::false_type{});
       }
 #pragma unroll
       for (int q = 0; q < NU3; ++q) {
@@ -295,39 +307,40 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
         const int cm = cin ? c : 0;
         const double *Ts = sg ? T5s : T2s;
         constexpr int GS3 = 3;  // kWideMaxNd <= 12
-        int lok[GS3], nk[GS3], oc[GS3];
-        bool ov[GS3];
+        // Per spin group s (this lane's spin value o = 4s + g): position p of the window is
+        // entry kb + p of the spin's k range, in range when 0 <= kb + p < nk (nk = 0 for a spin
+        // beyond nd or with an empty range); the operand rows of this lane start at tr and mr.
+        int kb[GS3], nk[GS3], tr[GS3], mr[GS3];
+        const double *bp[GS3];
 #pragma unroll
         for (int s = 0; s < GS3; ++s) {
-          const int o = 4 * s + g;
-          ov[s] = o < nd;
-          oc[s] = ov[s] ? o : 0;
-          lok[s] = rng[rlo * nd + oc[s]];
-          nk[s] = rng[(rlo + 1) * nd + oc[s]];
+          const int o = 4 * s + g, oc = o < nd ? o : 0;
+          const int lok = rng[rlo * nd + oc];
+          nk[s] = o < nd ? rng[(rlo + 1) * nd + oc] : 0;
+          kb[s] = (wlo - lok) >> 1;
+          tr[s] = (oc * 16 + c) * 16 + kb[s];
+          mr[s] = (mslot * nd + oc) * 256 + cm * 16 + kb[s];
+          bp[s] = B + bo[mslot * nd + oc] + (int64_t)cm * nk[s] + kb[s];
         }
         // Two positions at a time: the operand reads of both are in flight together and their
-        // two chains of multiply-adds interleave.
+        // two chains of multiply-adds interleave.  Both stages multiply T (lane c = row i5 or i2)
+        // by M (lane c = column i4 or i3): H comes out transposed, (i2, i3).
 #pragma unroll
         for (int pp = 0; pp < 2; ++pp) {
           double av[2][GS3], bv[2][GS3];
-          bool act[2];
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
             const int p = p0 + 2 * pp + q, kv = wlo + 2 * p;
-            act[q] = p >= pa && p <= pb;  // uniform
+            const bool act = p >= pa && p <= pb;  // uniform
 #pragma unroll
             for (int s = 0; s < GS3; ++s) {
-              const int ki = (kv - lok[s]) >> 1;
-              const bool ok = act[q] && ov[s] && nk[s] > 0 && kv >= lok[s] && ki < nk[s];
-              const int kc = ok ? ki : 0;
-              const double tv = Ts[(oc[s] * 16 + c) * 16 + kc];
-              // An empty block's offset may be the end of the booster buffer: read its start then.
-              const double *mp = ok ? B + bo[mslot * nd + oc[s]] + (int64_t)cm * nk[s] + kc : B;
-              const double mv = STG ? Mb[(mslot * nd + oc[s]) * 256 + cm * 16 + kc] : *mp * (double)(kv + 1);
-              // G: A = T5 (rows i5), B = M4 (columns i4); H: A = M3 (rows i3), B = T2 (columns i2).
-              const double x1 = ok ? tv : 0.0, x2 = (ok && cin) ? mv : 0.0;
-              av[q][s] = sg ? x1 : x2;
-              bv[q][s] = sg ? x2 : x1;
+              double x1 = 0.0, x2 = 0.0;
+              if (act && (unsigned)(kb[s] + p) < (unsigned)nk[s]) {
+                x1 = Ts[tr[s] + p];
+                x2 = STG ? Mb[mr[s] + p] : bp[s][p] * (double)(kv + 1);
+              }
+              av[q][s] = x1;
+              bv[q][s] = x2;
             }
           }
           d4v t[2] = {d4v{0.0, 0.0, 0.0, 0.0}, d4v{0.0, 0.0, 0.0, 0.0}};
@@ -348,10 +361,10 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
                 if (g + 4 * r < d5 && c < d4 && rho >= 0 && rho < nrow) Gs[rho * GS + p] = t[q][r];
               }
             } else {
-              // rows i3 = g + 4r, column i2 = c  ->  sig = i3 d2 + i2
+              // rows i2 = g + 4r, column i3 = c  ->  sig = i3 d2 + i2
 #pragma unroll
               for (int r = 0; r < 4; ++r)
-                if (g + 4 * r < d3 && c < d2) Hs[p * HS + (g + 4 * r) * d2 + c] = t[q][r];
+                if (g + 4 * r < d2 && c < d3) Hs[p * HS + c * d2 + g + 4 * r] = t[q][r];
             }
           }
         }
