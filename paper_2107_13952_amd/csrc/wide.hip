@@ -31,6 +31,14 @@ namespace eprl {
 
 namespace {
 
+// Device buffers reached through pointers held in memory (the batch kernel's parameter array)
+// are read and written as global memory: the compiler then emits global rather than generic
+// accesses, and waits on LDS reads no longer wait for them (a generic access counts for both).
+__device__ __forceinline__ double ldg(const double *p) {
+  return *(const __attribute__((address_space(1))) double *)p;
+}
+__device__ __forceinline__ void stg(double *p, double v) { *(__attribute__((address_space(1))) double *)p = v; }
+
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int WT = 512;          // threads per workgroup
@@ -164,7 +172,7 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
         const int lo = rng[ri * nd + o], n = rng[(ri + 1) * nd + o];
         const int di = slot == 0 ? d5 : slot == 1 ? d4 : slot == 2 ? d2 : d3;
         double v = 0.0;
-        if (i < di && k < n) v = B[bo[slot * nd + o] + (int64_t)i * n + k] * (double)(lo + 2 * k + 1);
+        if (i < di && k < n) v = ldg(B + bo[slot * nd + o] + (int64_t)i * n + k) * (double)(lo + 2 * k + 1);
         Mb[q] = v;
       }
       __syncthreads();
@@ -214,7 +222,7 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
         for (int q = 0; q < NU3; ++q) {
           const int idx = tid + q * WT, kp = idx >> 5, k3l = idx & 31;
           u3v[q] = 0.0;
-          if (kp >= a4l && kp <= b4l && k3l >= a3l && k3l <= b3l) u3v[q] = u3row[(int64_t)(k4g0 + kp) * nK3 + k3l];
+          if (kp >= a4l && kp <= b4l && k3l >= a3l && k3l <= b3l) u3v[q] = ldg(u3row + (int64_t)(k4g0 + kp) * nK3 + k3l);
         }
       }
 
@@ -260,8 +268,8 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
             const bool kin = ki >= ia && ki <= ib;
             const int kc = kin ? ki : ia;
             const double a = STG ? Mb[((s5 ? 0 : 2) * nd + o) * 256 + cr * 16 + kc]
-                                 : bm[kc] * (double)(lo + 2 * kc + 1);
-            const double b = P[(int64_t)(kgb + kc) * sP] * Q[(int64_t)(kgb + kc) * sQ];
+                                 : ldg(bm + kc) * (double)(lo + 2 * kc + 1);
+            const double b = ldg(P + (int64_t)(kgb + kc) * sP) * ldg(Q + (int64_t)(kgb + kc) * sQ);
             // k values outside [ia, ib] add nothing: zeroing one (finite) operand is enough.  Rows
             // c >= d5 (d2) and columns c >= np of T read clamped entries and are never used.
             av[s] = kin ? a : 0.0;
@@ -337,7 +345,7 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
               double x1 = 0.0, x2 = 0.0;
               if (act && (unsigned)(kb[s] + p) < (unsigned)nk[s]) {
                 x1 = Ts[tr[s] + p];
-                x2 = STG ? Mb[mr[s] + p] : bp[s][p] * (double)(kv + 1);
+                x2 = STG ? Mb[mr[s] + p] : ldg(bp[s] + p) * (double)(kv + 1);
               }
               av[q][s] = x1;
               bv[q][s] = x2;
@@ -448,7 +456,7 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
       const int rho = rho0 + rt * 16 + g + 4 * r;
       if (rho < geo.R && sig < geo.C) {
         const int i5 = rho / d4, i4 = rho - i5 * d4, i3 = sig / d2, i2 = sig - i3 * d2;
-        out[((i2 * d3 + i3) * d4 + i4) * d5 + i5] = acc[j][r];
+        stg(out + ((i2 * d3 + i3) * d4 + i4) * d5 + i5, acc[j][r]);
       }
     }
   }
