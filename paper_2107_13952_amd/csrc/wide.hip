@@ -361,18 +361,23 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
             const int p = p0 + 2 * pp + q;
+            // Entries outside the block go to a padding slot that nothing reads (column KW of
+            // G row c, column 16 CT of H row c), so the stores need no branch.
             if (sg) {
               // rows i5 = g + 4r, column i4 = c  ->  rho = i5 d4 + i4
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int rho = (g + 4 * r) * d4 + c - rho0;
-                if (g + 4 * r < d5 && c < d4 && rho >= 0 && rho < nrow) Gs[rho * GS + p] = t[q][r];
+                const bool ok = g + 4 * r < d5 && c < d4 && rho >= 0 && rho < nrow;
+                Gs[ok ? rho * GS + p : c * GS + KW] = t[q][r];
               }
             } else {
               // rows i2 = g + 4r, column i3 = c  ->  sig = i3 d2 + i2
 #pragma unroll
-              for (int r = 0; r < 4; ++r)
-                if (g + 4 * r < d2 && c < d3) Hs[p * HS + c * d2 + g + 4 * r] = t[q][r];
+              for (int r = 0; r < 4; ++r) {
+                const bool ok = g + 4 * r < d2 && c < d3;
+                Hs[ok ? p * HS + c * d2 + g + 4 * r : (c < KW ? c : 0) * HS + 16 * CT] = t[q][r];
+              }
             }
           }
         }
