@@ -165,15 +165,28 @@ __device__ void wide_item(const RingParams &rp, int chunk_index, int n1, int rb,
     }
     __syncthreads();
     if (STG) {
-      // Weighted booster blocks (2k+1) B of this core, zero outside each block.
-      for (int q = tid; q < 4 * nd * 256; q += WT) {
-        const int slot = q / (nd * 256), o = (q >> 8) % nd, i = (q >> 4) & 15, k = q & 15;
-        const int ri = slot == 0 ? 0 : slot == 1 ? 2 : slot == 2 ? 4 : 6;
-        const int lo = rng[ri * nd + o], n = rng[(ri + 1) * nd + o];
-        const int di = slot == 0 ? d5 : slot == 1 ? d4 : slot == 2 ? d2 : d3;
-        double v = 0.0;
-        if (i < di && k < n) v = ldg(B + bo[slot * nd + o] + (int64_t)i * n + k) * (double)(lo + 2 * k + 1);
-        Mb[q] = v;
+      // Weighted booster blocks (2k+1) B of this core, zero outside each block: block so =
+      // slot nd + o (slot 0 M5, 1 M4, 2 M2, 3 M3), entry (i, k) = thread (tid >> 4 & 15, tid & 15)
+      // of blocks tid >> 8, + 2, + 4, ...; the reads of eight blocks are in flight together.
+      {
+        const int i = (tid >> 4) & 15, k = tid & 15;
+        constexpr int kSB = 8;
+        for (int so0 = tid >> 8; so0 < 4 * nd; so0 += 2 * kSB) {
+          double v[kSB], wt[kSB];
+#pragma unroll
+          for (int j = 0; j < kSB; ++j) {
+            const int so = so0 + 2 * j;
+            const int slot = (so >= nd) + (so >= 2 * nd) + (so >= 3 * nd), o = so - slot * nd;
+            const int lo = rng[2 * slot * nd + o], n = rng[(2 * slot + 1) * nd + o];
+            const int di = slot == 0 ? d5 : slot == 1 ? d4 : slot == 2 ? d2 : d3;
+            wt[j] = (double)(lo + 2 * k + 1);
+            v[j] = 0.0;
+            if (so < 4 * nd && i < di && k < n) v[j] = ldg(B + bo[slot * nd + o] + (int64_t)i * n + k);
+          }
+#pragma unroll
+          for (int j = 0; j < kSB; ++j)
+            if (so0 + 2 * j < 4 * nd) Mb[(so0 + 2 * j) * 256 + (tid & 255)] = v[j] * wt[j];
+        }
       }
       __syncthreads();
     }
